@@ -1,0 +1,180 @@
+/*
+ * ntt_mi355x.h -- C ABI of the MI355X (gfx950) exact NTT library.
+ *
+ * Arithmetic is over F_p for primes p = k 2^l + 1 (section 1 of van der Hoeven,
+ * Lecerf, Quintin, "Modular SIMD arithmetic in Mathemagix"): residues are stored
+ * canonically in {0, ..., p-1} (section 2) as uint32 when p < 2^31 and uint64 when
+ * 2^31 <= p < 2^62.  The transform is the FFT of section 5.1,
+ *     a^_i = sum_j w^(i j) a_j,
+ * with w = g^((p-1)/n) for the plan's generator g; the bit-reversed ("TFT") order of
+ * section 5.1 places a^_[i]_k at position i.
+ *
+ * Conventions shared by every entry point:
+ *  - Every data pointer is a DEVICE pointer (hipMalloc / torch), 16-byte aligned,
+ *    owned by the caller.  The library owns only plan tables.
+ *  - Work is enqueued asynchronously on `hip_stream` (NULL = the default stream).
+ *    Argument errors are detected on the host and returned before anything is
+ *    enqueued; a failed launch returns NTT_EDEVICE.
+ *  - `workspace` is caller-owned device scratch of at least the size reported by
+ *    the matching *_workspace_bytes function; it may be NULL when that size is 0.
+ *  - Inputs must be canonical residues; only NTT_VALIDATE checks (synchronously).
+ *  - No C++ exception crosses this boundary.  Return value: NTT_OK or a negative
+ *    error code; ntt_last_error() gives a thread-local detail string.
+ */
+#ifndef NTT_MI355X_H
+#define NTT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NTT_OK = 0,
+  NTT_EINVAL = -1,        /* bad argument (NULL pointer, size, alignment, flags) */
+  NTT_ENOTPRIME = -2,     /* the modulus is not prime */
+  NTT_ENOROOT = -3,       /* 2^log2n does not divide p - 1, or g does not generate F_p^* */
+  NTT_ERANGE = -4,        /* NTT_VALIDATE found a non-canonical input */
+  NTT_ENOMEM = -5,        /* device allocation of plan tables failed, or workspace too small */
+  NTT_EDEVICE = -6,       /* a HIP call or kernel launch failed */
+  NTT_EUNSUPPORTED = -7   /* modulus outside [3, 2^62), or size beyond the library's limits */
+};
+
+/* Plan flags. */
+#define NTT_BITREV_OUT 1u /* forward leaves its output in bit-reversed (TFT) order     */
+#define NTT_BITREV_IN 2u  /* inverse takes its input in bit-reversed (TFT) order       */
+#define NTT_VALIDATE 4u   /* check that inputs are < p before launching (synchronous)   */
+
+typedef struct ntt_plan ntt_plan;
+
+typedef struct {
+  uint64_t p;         /* modulus                                              */
+  uint64_t g;         /* generator of F_p^* used for the roots                */
+  uint64_t w;         /* primitive n-th root of unity w = g^((p-1)/n)         */
+  uint64_t w_inv;     /* w^-1                                                 */
+  uint64_t n_inv;     /* n^-1 mod p                                           */
+  uint32_t log2n;     /* transform length n = 2^log2n                        */
+  uint32_t word_bits; /* 32 or 64: element type of the plan's vectors         */
+  uint32_t flags;     /* NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE        */
+  uint32_t passes;    /* number of HBM passes of one transform (1 = LDS-resident) */
+} ntt_plan_info;
+
+/* Polynomial-product descriptor for the batched entry point.  a, b, c are device
+ * pointers to uint32 (p < 2^31) or uint64 (p >= 2^31) residues; c receives
+ * la + lb - 1 coefficients (nothing when la or lb is 0). */
+typedef struct {
+  uint64_t p;
+  const void* a;
+  size_t la;
+  const void* b;
+  size_t lb;
+  void* c;
+} ntt_polymul_desc;
+
+/* Human-readable name of an error code (static storage). */
+const char* ntt_strerror(int code);
+
+/* Detail of the last error returned on the calling thread ("" if none). */
+const char* ntt_last_error(void);
+
+/* ---------------------------------------------------------------- host-only helpers
+ * These run on the CPU and touch no device. */
+
+/* 1 if n is prime (deterministic Miller-Rabin, valid for every 64-bit n), else 0. */
+int ntt_is_prime(uint64_t n);
+
+/* Smallest generator of F_p^* (0 if p is not prime). */
+uint64_t ntt_smallest_generator(uint64_t p);
+
+/* Largest prime p < 2^bits with p = 1 mod 2^l (p = k 2^l + 1), 0 if none;
+ * bits <= 63.  ntt_find_prime(62, 32) is the serving mix's ~62-bit prime. */
+uint64_t ntt_find_prime(uint32_t bits, uint32_t l);
+
+/* ---------------------------------------------------------------- transforms
+ * Section 5.1: FFT_w of length n = 2^log2n over F_p. */
+
+/* Create a plan for length 2^log2n (0 <= log2n <= l where p = k 2^l + 1) modulo p.
+ * g = 0 selects the smallest generator; otherwise g must generate F_p^*.
+ * The plan precomputes and uploads its twiddle tables (section 5.1: "all the
+ * necessary primitive roots and powers are pre-computed and cached") with
+ * synchronous copies; `hip_stream` is unused at creation and may be NULL.
+ * A plan is immutable after creation and may be used concurrently on different
+ * streams.  Errors: NTT_EINVAL (out == NULL, unknown flags), NTT_EUNSUPPORTED
+ * (p < 3 or p >= 2^62, log2n > 26), NTT_ENOTPRIME, NTT_ENOROOT, NTT_ENOMEM. */
+int ntt_plan_create(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags, void* hip_stream);
+
+/* Free a plan and its device tables.  NULL is accepted.  The caller must make sure
+ * no enqueued work still uses it. */
+int ntt_plan_destroy(ntt_plan* plan);
+
+int ntt_plan_get_info(const ntt_plan* plan, ntt_plan_info* info);
+
+/* Device scratch needed by ntt_forward / ntt_inverse for `batch` vectors. */
+size_t ntt_workspace_bytes(const ntt_plan* plan, size_t batch);
+
+/* Forward transform of `batch` vectors of n residues.  Vector b starts at
+ * in + b * stride_elems (elements, stride_elems >= n).  in == out is allowed.
+ * Output order: natural (out_i = a^_i), or bit-reversed with NTT_BITREV_OUT.
+ * Errors: NTT_EINVAL (NULL/misaligned pointer, stride < n), NTT_ENOMEM (workspace
+ * too small), NTT_ERANGE (NTT_VALIDATE only), NTT_EDEVICE. */
+int ntt_forward(const ntt_plan* plan, const void* in, void* out, size_t batch, size_t stride_elems,
+                void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* Inverse transform: FFT_{w^-1} followed by multiplication by n^-1, so that
+ * ntt_inverse(ntt_forward(a)) = a exactly (section 5.1: invert the steps and use the
+ * inverse transform).  Input order natural, or bit-reversed with NTT_BITREV_IN.
+ * Same arguments and errors as ntt_forward. */
+int ntt_inverse(const ntt_plan* plan, const void* in, void* out, size_t batch, size_t stride_elems,
+                void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* ---------------------------------------------------------------- polynomial products
+ * Section 5.2: the product of two polynomials over F_p by two forward transforms,
+ * an entry-wise product and one inverse transform, after zero padding to the
+ * transform length N = the smallest power of two >= la + lb - 1. */
+
+size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb);
+
+/* c[0 .. la+lb-2] = a * b mod p (linear product; c has la + lb - 1 entries).
+ * la == 0 or lb == 0: nothing is written, NTT_OK.  Element type: uint32 when
+ * p < 2^31, else uint64.  Plans (tables) are created on first use per (device, p)
+ * and cached for the life of the process.
+ * Errors: NTT_EINVAL, NTT_ENOTPRIME, NTT_ENOROOT (N > 2^l), NTT_EUNSUPPORTED,
+ * NTT_ENOMEM, NTT_EDEVICE. */
+int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
+                 size_t ws_bytes, void* hip_stream);
+
+/* Device scratch for polymul_modp_batch on these descriptors. */
+size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
+
+/* All `count` products in as few launches as the sizes allow: every descriptor
+ * whose transform fits one workgroup (N <= 2^16 for 32-bit, 2^15 for 64-bit
+ * primes) is served by ONE persistent fused launch (fold, forward x2, entry-wise
+ * product, inverse, combine) whatever its prime and length (section 2.2, Remark 6:
+ * several moduli in one vector launch); larger ones run the multi-pass path.
+ * `d` is a HOST array; its content is copied into the workspace.
+ * Errors as polymul_modp, checked for every descriptor before anything runs. */
+int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes,
+                       void* hip_stream);
+
+/* ---------------------------------------------------------------- integer product
+ * Section 5.3: Kronecker segmentation with 16-bit chunks (A(2^16) = a) and the
+ * three-prime transform over p1 = 998244353, p2 = 469762049, p3 = 167772161,
+ * Chinese remaindering (Garner) and carry propagation. */
+
+size_t intmul_workspace_bytes(size_t na, size_t nb);
+
+/* c = a * b for nonnegative integers given as little-endian 16-bit limbs (device
+ * pointers).  c receives exactly ceil((na + nb) / 2) little-endian 32-bit limbs,
+ * unnormalised (leading zero limbs allowed).  na == 0 or nb == 0 writes zeros.
+ * Errors: NTT_EINVAL (NULL pointers, na + nb - 1 > 2^23: the smallest 2-adic
+ * order of the three primes is 23), NTT_ENOMEM (workspace), NTT_EDEVICE. */
+int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint32_t* c, void* workspace,
+               size_t ws_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NTT_MI355X_H */

@@ -1,0 +1,122 @@
+// Device modular arithmetic for gfx950 (section 2 of the paper, re-designed for a
+// 64-lane wavefront: one residue per lane, no lane splitting).
+//
+// Word model: T = uint32_t for p < 2^31, T = uint64_t for p < 2^62 (section 2: U of
+// n bits, p of at most m bits).  Measured on gfx950, v_mul_lo_u32, v_mul_hi_u32 and
+// v_mad_u64_u32 issue at the same rate as v_min_u32, so the fixed-multiplicand
+// product costs three multiplies and one subtraction, with no special-form tricks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nttgpu {
+
+template <typename T>
+struct TwPair {
+  T w;   // twiddle value, canonical
+  T ws;  // floor(w * 2^bits(T) / p): the precomputed multiplicand of Function 8
+};
+
+template <typename T>
+struct Arith;
+
+// 32-bit residues, p < 2^31.
+template <>
+struct Arith<uint32_t> {
+  uint32_t p, p2, pinv;  // p, 2p, p^-1 mod 2^32
+
+  // Function 8 (fixed multiplicand y = w, psi = ws) with the final correction left
+  // out: for ANY x < 2^32 the result x w - floor(x ws / 2^32) p lies in [0, 2p)
+  // (Proposition 4's bound with x not reduced), computed modulo 2^32 since 2p < 2^32.
+  __device__ __forceinline__ uint32_t shoup(uint32_t x, uint32_t w, uint32_t ws) const {
+    uint32_t q = __umulhi(x, ws);
+    return x * w - q * p;
+  }
+  // Function 2's min trick: [0, 2p) -> [0, p) and [0, 4p) -> [0, 2p).
+  __device__ __forceinline__ uint32_t red1(uint32_t x) const { return min(x, x - p); }
+  __device__ __forceinline__ uint32_t red2(uint32_t x) const { return min(x, x - p2); }
+  // Function 13 (Montgomery, m = n = 32) on a = x y < 2^32 p, with the sign
+  // convention chi' = p^-1: returns x y 2^-32 mod p in (0, 2p).
+  __device__ __forceinline__ uint32_t mont(uint32_t x, uint32_t y) const {
+    uint64_t t = (uint64_t)x * y;
+    uint32_t m = (uint32_t)t * pinv;
+    return (uint32_t)(t >> 32) - __umulhi(m, p) + p;
+  }
+};
+
+// 64-bit residues, p < 2^62 (so 4p < 2^64 and every lazy range fits).
+template <>
+struct Arith<uint64_t> {
+  uint64_t p, p2, pinv;
+
+  __device__ __forceinline__ uint64_t shoup(uint64_t x, uint64_t w, uint64_t ws) const {
+    uint64_t q = __umul64hi(x, ws);
+    return x * w - q * p;
+  }
+  __device__ __forceinline__ uint64_t red1(uint64_t x) const {
+    uint64_t y = x - p;
+    return x < p ? x : y;
+  }
+  __device__ __forceinline__ uint64_t red2(uint64_t x) const {
+    uint64_t y = x - p2;
+    return x < p2 ? x : y;
+  }
+  __device__ __forceinline__ uint64_t mont(uint64_t x, uint64_t y) const {
+    uint64_t lo = x * y;
+    uint64_t hi = __umul64hi(x, y);
+    uint64_t m = lo * pinv;
+    return hi - __umul64hi(m, p) + p;
+  }
+};
+
+// ----------------------------------------------------------------------------
+// Butterflies.  LAZY (4p < 2^bits): Harvey-style ranges; otherwise (the 31-bit
+// primes) every sum is formed from operands reduced to [0, p).
+//
+// Forward, Cooley-Tukey form (X, Y) -> (X + w Y, X - w Y):
+//   LAZY: X in [0,4p), Y < 2^bits  ->  both outputs in [0,4p)
+//   SAFE: X in [0,2p), Y < 2^bits  ->  both outputs in [0,2p)
+template <bool LAZY, typename T>
+__device__ __forceinline__ void ct_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
+  T t = ar.shoup(Y, tw.w, tw.ws);
+  if constexpr (LAZY) {
+    T x = ar.red2(X);
+    X = x + t;
+    Y = x - t + ar.p2;
+  } else {
+    T x = ar.red1(X);
+    t = ar.red1(t);
+    X = x + t;
+    Y = x - t + ar.p;
+  }
+}
+
+// Inverse, Gentleman-Sande form (X, Y) -> (X + Y, (X - Y) w):
+//   LAZY: inputs in [0,2p) -> outputs in [0,2p)
+//   SAFE: inputs in [0,p)  -> outputs in [0,p)
+template <bool LAZY, typename T>
+__device__ __forceinline__ void gs_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
+  if constexpr (LAZY) {
+    T s = ar.red2(X + Y);
+    Y = ar.shoup(X - Y + ar.p2, tw.w, tw.ws);
+    X = s;
+  } else {
+    T s = ar.red1(X + Y);
+    Y = ar.red1(ar.shoup(X - Y + ar.p, tw.w, tw.ws));
+    X = s;
+  }
+}
+
+// Canonical representative from the range a butterfly left behind.
+template <bool LAZY, typename T>
+__device__ __forceinline__ T canon_from_fwd(const Arith<T>& ar, T x) {
+  if constexpr (LAZY) return ar.red1(ar.red2(x));
+  else return ar.red1(x);
+}
+template <bool LAZY, typename T>
+__device__ __forceinline__ T canon_from_inv(const Arith<T>& ar, T x) {
+  if constexpr (LAZY) return ar.red1(x);
+  else return x;
+}
+
+}  // namespace nttgpu

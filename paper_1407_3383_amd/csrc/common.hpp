@@ -1,0 +1,47 @@
+// Types shared by the host library and the kernels (device-resident descriptors).
+#pragma once
+#include <stdint.h>
+
+#include "arith.hpp"
+
+namespace nttgpu {
+
+// Per-(p, transform length) constants of the fused product (device memory).
+// d = log2 N - m is the split depth: the product runs as 2^d sub-problems of length
+// 2^m (section 5.1's Algorithm 1 with n1 = 2^d), each sub-problem h starting from the
+// fold sum_k a[j + k 2^m] psi_h^k, psi_h = w_{2^d}^([h]_d).
+template <typename T>
+struct PolyConst {
+  T p, p2, pinv, lazy;  // lazy = 1 when 4p < 2^bits(T)
+  TwPair<T> fa[4][4];   // psi_h^k
+  TwPair<T> fb[4][4];   // psi_h^k * sigma, sigma = 2^bits(T) / N mod p (Montgomery scale)
+};
+
+// One product in a fused launch.
+struct FusedItem {
+  const void* a;
+  const void* b;
+  void* c;
+  uint64_t la, lb;
+  const void* cst;  // PolyConst<T>
+  const void* tw;   // TwPair<T>[2^LT]: forward universal table
+  const void* twi;  // TwPair<T>[2^LT]: inverse universal table
+  uint32_t log2n;
+  uint32_t pad;
+};
+
+// Per-plan constants of a multi-pass transform of length 2^L = 2^L1 * 2^L2.
+// Pass 1 (columns) transforms the 2^L2 strided vectors of length 2^L1 with the
+// universal table; pass 2 (rows) twists row r (of length 2^L2) by G^j,
+// G = w_N^([r]_L1), then transforms it (Algorithm 1, steps 2 and 3).  G^j =
+// w_N^e with e = j [r]_L1 < N is read from two tables: w_N^e = lo[e & (2^B-1)] *
+// hi[e >> B].
+template <typename T>
+struct PassConst {
+  T p, p2, pinv, lazy;
+  TwPair<T> ninv;     // n^-1
+  TwPair<T> sigma;    // 2^bits(T) / N mod p
+  uint32_t L, L1, L2, B;
+};
+
+}  // namespace nttgpu

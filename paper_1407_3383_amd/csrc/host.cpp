@@ -1,0 +1,1039 @@
+// Host side of the library: number theory, plan tables, argument checking and the
+// launch sequences behind the C ABI of include/ntt_mi355x.h.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ntt_mi355x.h"
+#include "kernels.hpp"
+
+using namespace nttgpu;
+
+typedef unsigned __int128 u128;
+
+// ============================================================================ errors
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return NTT_OK;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(NTT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ============================================================================ number theory
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  a %= m;
+  while (e) {
+    if (e & 1) r = mulmod(r, a, m);
+    a = mulmod(a, a, m);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Miller-Rabin with the first twelve prime bases: deterministic for all n < 2^64.
+bool is_prime_u64(uint64_t n) {
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return false;
+  for (uint64_t b : bases)
+    if (n % b == 0) return n == b;
+  uint64_t d = n - 1;
+  int s = 0;
+  while ((d & 1) == 0) {
+    d >>= 1;
+    ++s;
+  }
+  for (uint64_t b : bases) {
+    uint64_t x = powmod(b, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool composite = true;
+    for (int i = 1; i < s; ++i) {
+      x = mulmod(x, x, n);
+      if (x == n - 1) {
+        composite = false;
+        break;
+      }
+    }
+    if (composite) return false;
+  }
+  return true;
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Pollard-Brent rho: a nontrivial factor of the composite odd n.
+uint64_t rho_factor(uint64_t n) {
+  for (uint64_t c = 1;; ++c) {
+    uint64_t y = 2, x = 2, g = 1, q = 1, ys = 2;
+    uint64_t r = 1;
+    const uint64_t m = 128;
+    auto f = [&](uint64_t v) { return (mulmod(v, v, n) + c) % n; };
+    do {
+      x = y;
+      for (uint64_t i = 0; i < r; ++i) y = f(y);
+      uint64_t k = 0;
+      do {
+        ys = y;
+        for (uint64_t i = 0; i < std::min(m, r - k); ++i) {
+          y = f(y);
+          q = mulmod(q, x > y ? x - y : y - x, n);
+        }
+        g = gcd_u64(q, n);
+        k += m;
+      } while (k < r && g == 1);
+      r <<= 1;
+    } while (g == 1);
+    if (g == n) {
+      do {
+        ys = f(ys);
+        g = gcd_u64(x > ys ? x - ys : ys - x, n);
+      } while (g == 1);
+    }
+    if (g != n) return g;
+  }
+}
+
+void factor_into(uint64_t n, std::vector<uint64_t>& out) {
+  if (n == 1) return;
+  for (uint64_t q = 2; q < 1000 && q * q <= n; ++q) {
+    if (n % q == 0) {
+      out.push_back(q);
+      while (n % q == 0) n /= q;
+    }
+  }
+  if (n == 1) return;
+  if (is_prime_u64(n)) {
+    out.push_back(n);
+    return;
+  }
+  uint64_t f = rho_factor(n);
+  factor_into(f, out);
+  factor_into(n / f, out);
+}
+
+std::vector<uint64_t> distinct_prime_factors(uint64_t n) {
+  std::vector<uint64_t> f;
+  factor_into(n, f);
+  std::sort(f.begin(), f.end());
+  f.erase(std::unique(f.begin(), f.end()), f.end());
+  return f;
+}
+
+bool generates(uint64_t g, uint64_t p, const std::vector<uint64_t>& qs) {
+  if (g % p == 0) return false;
+  for (uint64_t q : qs)
+    if (powmod(g, (p - 1) / q, p) == 1) return false;
+  return true;
+}
+
+uint64_t smallest_generator(uint64_t p) {
+  const std::vector<uint64_t> qs = distinct_prime_factors(p - 1);
+  for (uint64_t g = 2; g < p; ++g)
+    if (generates(g, p, qs)) return g;
+  return 0;
+}
+
+int two_adic_order(uint64_t p) {
+  uint64_t k = p - 1;
+  int l = 0;
+  while (k && (k & 1) == 0) {
+    k >>= 1;
+    ++l;
+  }
+  return l;
+}
+
+uint64_t invmod(uint64_t a, uint64_t p) { return powmod(a, p - 2, p); }
+
+uint32_t brev(uint32_t i, int k) {
+  uint32_t r = 0;
+  for (int b = 0; b < k; ++b) r |= ((i >> b) & 1u) << (k - 1 - b);
+  return r;
+}
+
+int ceil_log2(uint64_t n) {
+  int L = 0;
+  while ((1ull << L) < n) ++L;
+  return L;
+}
+
+// ============================================================================ tables
+constexpr int kUniversalMaxLog = 16;
+
+template <typename T>
+TwPair<T> pair_of(uint64_t w, uint64_t p) {
+  TwPair<T> t;
+  t.w = (T)w;
+  t.ws = (T)(((u128)w << (8 * sizeof(T))) / p);
+  return t;
+}
+
+// Universal bit-reversed tables: tw[2^s + i] = w_{2^(s+1)}^([i]_s) for s < LT.
+template <typename T>
+void build_universal(uint64_t p, uint64_t g, int LT, bool inverse, std::vector<TwPair<T>>& out) {
+  out.assign((size_t)1 << LT, pair_of<T>(1, p));
+  std::vector<uint64_t> pw;
+  for (int s = 0; s < LT; ++s) {
+    uint64_t w = powmod(g, (p - 1) >> (s + 1), p);
+    if (inverse) w = invmod(w, p);
+    pw.assign((size_t)1 << s, 1);
+    for (size_t e = 1; e < pw.size(); ++e) pw[e] = mulmod(pw[e - 1], w, p);
+    for (uint32_t i = 0; i < (1u << s); ++i) out[((size_t)1 << s) + i] = pair_of<T>(pw[brev(i, s)], p);
+  }
+}
+
+template <typename T>
+void build_powers(uint64_t base, uint64_t p, size_t n, uint64_t scale, std::vector<TwPair<T>>& out) {
+  out.resize(n);
+  uint64_t x = scale % p;
+  for (size_t e = 0; e < n; ++e) {
+    out[e] = pair_of<T>(x, p);
+    x = mulmod(x, base, p);
+  }
+}
+
+uint64_t inv_pow2_word(uint64_t p, int bits) {  // p^-1 mod 2^bits by Newton iteration
+  uint64_t x = p;  // correct to 3 bits for odd p
+  for (int i = 0; i < 6; ++i) x *= 2 - p * x;
+  if (bits == 32) x &= 0xFFFFFFFFull;
+  return x;
+}
+
+}  // namespace
+
+// ============================================================================ plan
+struct ntt_plan {
+  uint64_t p, g, w, winv, ninv;
+  uint32_t log2n, wbits, flags, passes, L1, L2, B, LT;
+  int device;
+  bool lazy;
+  void* dmem;
+  size_t dbytes;
+  const void *tw, *twi, *tlo, *thi, *tilo, *tihi, *tihin, *polyc, *passc;
+};
+
+namespace {
+
+struct Blob {
+  std::vector<unsigned char> bytes;
+  size_t add(const void* src, size_t n) {
+    size_t off = (bytes.size() + 255) & ~(size_t)255;
+    bytes.resize(off + n);
+    memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+template <typename T>
+int build_plan_tables(ntt_plan* pl) {
+  const uint64_t p = pl->p;
+  const int L = (int)pl->log2n;
+  const int W = (int)(8 * sizeof(T));
+  Blob blob;
+  std::vector<TwPair<T>> tw, twi;
+  pl->LT = (uint32_t)std::max(1, std::min(L, kUniversalMaxLog));
+  build_universal<T>(p, pl->g, (int)pl->LT, false, tw);
+  build_universal<T>(p, pl->g, (int)pl->LT, true, twi);
+  const size_t o_tw = blob.add(tw.data(), tw.size() * sizeof(TwPair<T>));
+  const size_t o_twi = blob.add(twi.data(), twi.size() * sizeof(TwPair<T>));
+
+  const uint64_t N = 1ull << L;
+  const uint64_t sigma = mulmod((uint64_t)((((u128)1) << W) % p), pl->ninv, p);
+
+  // Fused-product constants.
+  PolyConst<T> pc;
+  memset(&pc, 0, sizeof(pc));
+  pc.p = (T)p;
+  pc.p2 = (T)(2 * p);
+  pc.pinv = (T)inv_pow2_word(p, W);
+  pc.lazy = (T)(pl->lazy ? 1 : 0);
+  {
+    const int lmax = (W == 32) ? 14 : 13;
+    const int d = L > lmax ? L - lmax : 0;
+    const uint64_t root_d = powmod(pl->g, (p - 1) >> d, p);  // w_{2^d}
+    for (int h = 0; h < 4; ++h) {
+      const uint64_t psi = (h < (1 << d)) ? powmod(root_d, brev((uint32_t)h, d), p) : 1;
+      uint64_t x = 1;
+      for (int k = 0; k < 4; ++k) {
+        pc.fa[h][k] = pair_of<T>(x, p);
+        pc.fb[h][k] = pair_of<T>(mulmod(x, sigma, p), p);
+        x = mulmod(x, psi, p);
+      }
+    }
+  }
+  const size_t o_pc = blob.add(&pc, sizeof(pc));
+
+  // Two-pass constants and twist tables.
+  PassConst<T> sc;
+  memset(&sc, 0, sizeof(sc));
+  sc.p = (T)p;
+  sc.p2 = (T)(2 * p);
+  sc.pinv = (T)inv_pow2_word(p, W);
+  sc.lazy = (T)(pl->lazy ? 1 : 0);
+  sc.ninv = pair_of<T>(pl->ninv, p);
+  sc.sigma = pair_of<T>(sigma, p);
+  sc.L = (uint32_t)L;
+  sc.L1 = pl->L1;
+  sc.L2 = pl->L2;
+  sc.B = pl->B;
+  const size_t o_sc = blob.add(&sc, sizeof(sc));
+  size_t o_lo = 0, o_hi = 0, o_ilo = 0, o_ihi = 0, o_ihin = 0;
+  if (pl->passes > 1) {
+    const int B = (int)pl->B;
+    std::vector<TwPair<T>> lo, hi, ilo, ihi, ihin;
+    build_powers<T>(pl->w, p, (size_t)1 << B, 1, lo);
+    build_powers<T>(powmod(pl->w, 1ull << B, p), p, (size_t)1 << (L - B), 1, hi);
+    build_powers<T>(pl->winv, p, (size_t)1 << B, 1, ilo);
+    build_powers<T>(powmod(pl->winv, 1ull << B, p), p, (size_t)1 << (L - B), 1, ihi);
+    build_powers<T>(powmod(pl->winv, 1ull << B, p), p, (size_t)1 << (L - B), pl->ninv, ihin);
+    o_lo = blob.add(lo.data(), lo.size() * sizeof(TwPair<T>));
+    o_hi = blob.add(hi.data(), hi.size() * sizeof(TwPair<T>));
+    o_ilo = blob.add(ilo.data(), ilo.size() * sizeof(TwPair<T>));
+    o_ihi = blob.add(ihi.data(), ihi.size() * sizeof(TwPair<T>));
+    o_ihin = blob.add(ihin.data(), ihin.size() * sizeof(TwPair<T>));
+  }
+  (void)N;
+  void* d = nullptr;
+  if (hipMalloc(&d, blob.bytes.size()) != hipSuccess)
+    return fail(NTT_ENOMEM, "hipMalloc of %zu bytes of plan tables failed", blob.bytes.size());
+  if (hipMemcpy(d, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(NTT_EDEVICE, "upload of plan tables failed");
+  }
+  unsigned char* base = (unsigned char*)d;
+  pl->dmem = d;
+  pl->dbytes = blob.bytes.size();
+  pl->tw = base + o_tw;
+  pl->twi = base + o_twi;
+  pl->polyc = base + o_pc;
+  pl->passc = base + o_sc;
+  pl->tlo = pl->passes > 1 ? base + o_lo : nullptr;
+  pl->thi = pl->passes > 1 ? base + o_hi : nullptr;
+  pl->tilo = pl->passes > 1 ? base + o_ilo : nullptr;
+  pl->tihi = pl->passes > 1 ? base + o_ihi : nullptr;
+  pl->tihin = pl->passes > 1 ? base + o_ihin : nullptr;
+  return NTT_OK;
+}
+
+const uint64_t kMaxModulus = 1ull << 62;
+
+int check_modulus(uint64_t p, int* l_out) {
+  if (p < 3 || p >= kMaxModulus) return fail(NTT_EUNSUPPORTED, "modulus %llu outside [3, 2^62)", (unsigned long long)p);
+  if (!is_prime_u64(p)) return fail(NTT_ENOTPRIME, "modulus %llu is not prime", (unsigned long long)p);
+  *l_out = two_adic_order(p);
+  return NTT_OK;
+}
+
+int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags) {
+  int l = 0;
+  int rc = check_modulus(p, &l);
+  if (rc) return rc;
+  if (log2n > 26) return fail(NTT_EUNSUPPORTED, "log2n = %u exceeds 26", log2n);
+  if ((int)log2n > l)
+    return fail(NTT_ENOROOT, "2^%u does not divide p - 1 (2-adic order %d)", log2n, l);
+  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE)) return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
+  if (g == 0) {
+    g = smallest_generator(p);
+  } else if (!generates(g, p, distinct_prime_factors(p - 1))) {
+    return fail(NTT_ENOROOT, "%llu does not generate F_p^*", (unsigned long long)g);
+  }
+  ntt_plan* pl = new (std::nothrow) ntt_plan();
+  if (!pl) return fail(NTT_ENOMEM, "host allocation failed");
+  pl->p = p;
+  pl->g = g;
+  pl->log2n = log2n;
+  pl->flags = flags;
+  pl->wbits = p < (1ull << 31) ? 32 : 64;
+  pl->lazy = pl->wbits == 64 ? true : (p < (1ull << 30));
+  pl->w = powmod(g, (p - 1) >> log2n, p);
+  pl->winv = invmod(pl->w, p);
+  pl->ninv = invmod((1ull << log2n) % p, p);
+  const int wb = (int)pl->wbits;
+  if ((int)log2n <= lds_max_log2n(wb)) {
+    pl->passes = 1;
+    pl->L1 = 0;
+    pl->L2 = log2n;
+  } else {
+    pl->passes = 2;
+    pl->L2 = (uint32_t)pass_max_row_log2(wb);
+    pl->L1 = log2n - pl->L2;
+  }
+  pl->B = (log2n + 1) / 2;
+  if (hipGetDevice(&pl->device) != hipSuccess) {
+    delete pl;
+    return fail(NTT_EDEVICE, "hipGetDevice failed");
+  }
+  rc = pl->wbits == 32 ? build_plan_tables<uint32_t>(pl) : build_plan_tables<uint64_t>(pl);
+  if (rc) {
+    delete pl;
+    return rc;
+  }
+  *out = pl;
+  return NTT_OK;
+}
+
+// ============================================================================ per-device context
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+
+struct DeviceCtx {
+  std::mutex mu;
+  std::map<std::pair<uint64_t, uint32_t>, ntt_plan*> plans;
+  Staging ring[8];
+  unsigned next = 0;
+  int cus = 0;
+  uint32_t* flag = nullptr;
+};
+
+std::mutex g_ctx_mu;
+std::map<int, DeviceCtx*> g_ctx;
+
+DeviceCtx* device_ctx(int dev) {
+  std::lock_guard<std::mutex> lk(g_ctx_mu);
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) return it->second;
+  DeviceCtx* c = new DeviceCtx();
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  c->cus = cus;
+  g_ctx[dev] = c;
+  return c;
+}
+
+// Cached plan for (current device, p, log2n) with the smallest generator.
+int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_EDEVICE, "hipGetDevice failed");
+  DeviceCtx* c = device_ctx(dev);
+  std::lock_guard<std::mutex> lk(c->mu);
+  auto key = std::make_pair(p, log2n);
+  auto it = c->plans.find(key);
+  if (it != c->plans.end()) {
+    *out = it->second;
+    return NTT_OK;
+  }
+  ntt_plan* pl = nullptr;
+  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN);
+  if (rc) return rc;
+  c->plans[key] = pl;
+  *out = pl;
+  return NTT_OK;
+}
+
+// Copies `bytes` of host data into device memory `dst` on `stream` through a pinned
+// staging slot; the slot is reused only after the copy that used it has completed.
+int upload(DeviceCtx* c, void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  if (bytes == 0) return NTT_OK;
+  std::lock_guard<std::mutex> lk(c->mu);
+  Staging& s = c->ring[c->next++ % 8];
+  if (s.pending) {
+    HIP_TRY(hipEventSynchronize(s.ev));
+    s.pending = false;
+  }
+  if (!s.ev) HIP_TRY(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+  if (s.cap < bytes) {
+    if (s.host) HIP_TRY(hipHostFree(s.host));
+    s.host = nullptr;
+    size_t cap = std::max(bytes, (size_t)65536);
+    HIP_TRY(hipHostMalloc(&s.host, cap, hipHostMallocDefault));
+    s.cap = cap;
+  }
+  memcpy(s.host, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipEventRecord(s.ev, stream));
+  s.pending = true;
+  return NTT_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool aligned_to(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+// Synchronous check that every element of `batch` vectors is < p (NTT_VALIDATE).
+int validate_range(int wb, const void* x, size_t n, size_t stride, size_t batch, uint64_t p, hipStream_t stream) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceCtx* c = device_ctx(dev);
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (!c->flag) HIP_TRY(hipMalloc((void**)&c->flag, sizeof(uint32_t)));
+  HIP_TRY(launch_fill_u32(c->flag, 1, 0u, stream));
+  HIP_TRY(launch_range_check(wb, x, n, stride, (uint32_t)batch, p, c->flag, stream));
+  uint32_t h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->flag, sizeof(h), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (h) return fail(NTT_ERANGE, "input holds a value >= p = %llu", (unsigned long long)p);
+  return NTT_OK;
+}
+
+// ---------------------------------------------------------------------------- transforms
+int run_transform(const ntt_plan* pl, bool inverse, const void* in, void* out, size_t batch, size_t stride,
+                  void* ws, size_t wsb, hipStream_t stream) {
+  if (!pl) return fail(NTT_EINVAL, "plan is NULL");
+  const size_t n = (size_t)1 << pl->log2n;
+  const size_t esz = pl->wbits / 8;
+  if (batch == 0) return ok();
+  if (!in || !out) return fail(NTT_EINVAL, "NULL vector pointer");
+  if (!aligned_to(in, esz) || !aligned_to(out, esz)) return fail(NTT_EINVAL, "vectors must be %zu-byte aligned", esz);
+  if (stride < n) return fail(NTT_EINVAL, "stride %zu < n = %zu", stride, n);
+  if (batch > 0xFFFFFFFFull) return fail(NTT_EINVAL, "batch too large");
+  const size_t need = ntt_workspace_bytes(pl, batch);
+  if (wsb < need || (need && !ws)) return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, wsb);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != pl->device) return fail(NTT_EINVAL, "plan belongs to device %d, current device is %d", pl->device, dev);
+  const int wb = (int)pl->wbits;
+  if (pl->flags & NTT_VALIDATE) {
+    int rc = validate_range(wb, in, n, stride, batch, pl->p, stream);
+    if (rc) return rc;
+  }
+  if (pl->passes == 1) {
+    LdsNttArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = in;
+    a.out = out;
+    a.stride = stride;
+    a.pc = pl->passc;
+    a.tw = pl->tw;
+    a.twi = pl->twi;
+    a.L = pl->log2n;
+    a.bitrev = inverse ? ((pl->flags & NTT_BITREV_IN) ? 1 : 0) : ((pl->flags & NTT_BITREV_OUT) ? 1 : 0);
+    a.batch = (uint32_t)batch;
+    HIP_TRY(launch_lds_ntt(wb, inverse, a, stream));
+    return ok();
+  }
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pc = pl->passc;
+  a.tw = pl->tw;
+  a.twi = pl->twi;
+  a.tlo = pl->tlo;
+  a.thi = pl->thi;
+  a.tilo = pl->tilo;
+  a.tihi = pl->tihin;  // the inverse transform includes n^-1
+  a.batch = (uint32_t)batch;
+  a.valid = n;
+  const int L1 = (int)pl->L1, L2 = (int)pl->L2;
+  if (!inverse) {
+    const bool natural = !(pl->flags & NTT_BITREV_OUT);
+    void* X = natural ? ws : out;
+    const size_t xs = natural ? n : stride;
+    a.in = in;
+    a.in_stride = stride;
+    a.out = X;
+    a.out_stride = xs;
+    HIP_TRY(launch_col_fwd(wb, a, L1, L2, stream));
+    a.in = X;
+    a.in_stride = xs;
+    HIP_TRY(launch_row_fwd(wb, a, L1, L2, stream));
+    if (natural) HIP_TRY(launch_bitrev_permute(wb, X, out, xs, stride, pl->log2n, (uint32_t)batch, stream));
+  } else {
+    const bool natural = !(pl->flags & NTT_BITREV_IN);
+    const void* src = in;
+    size_t ss = stride;
+    if (natural) {
+      HIP_TRY(launch_bitrev_permute(wb, in, ws, stride, n, pl->log2n, (uint32_t)batch, stream));
+      src = ws;
+      ss = n;
+    }
+    a.in = src;
+    a.in_stride = ss;
+    a.out = natural ? ws : out;
+    a.out_stride = natural ? n : stride;
+    HIP_TRY(launch_row_inv(wb, a, L1, L2, true, stream));
+    a.in = a.out;
+    a.in_stride = a.out_stride;
+    a.out = out;
+    a.out_stride = stride;
+    HIP_TRY(launch_col_inv(wb, a, L1, L2, stream));
+  }
+  return ok();
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char* ntt_strerror(int code) {
+  switch (code) {
+    case NTT_OK: return "success";
+    case NTT_EINVAL: return "invalid argument";
+    case NTT_ENOTPRIME: return "modulus is not prime";
+    case NTT_ENOROOT: return "no root of unity of the requested order";
+    case NTT_ERANGE: return "input is not a canonical residue";
+    case NTT_ENOMEM: return "out of memory or workspace too small";
+    case NTT_EDEVICE: return "device error";
+    case NTT_EUNSUPPORTED: return "unsupported modulus or size";
+    default: return "unknown error";
+  }
+}
+
+const char* ntt_last_error(void) { return g_last_error.c_str(); }
+
+int ntt_is_prime(uint64_t n) { return is_prime_u64(n) ? 1 : 0; }
+
+uint64_t ntt_smallest_generator(uint64_t p) { return is_prime_u64(p) ? smallest_generator(p) : 0; }
+
+uint64_t ntt_find_prime(uint32_t bits, uint32_t l) {
+  if (bits < 2 || bits > 63 || l >= bits) return 0;
+  const uint64_t bound = 1ull << bits;
+  for (uint64_t k = (bound - 2) >> l; k > 0; --k) {
+    const uint64_t p = (k << l) + 1;
+    if (p < bound && is_prime_u64(p)) return p;
+  }
+  return 0;
+}
+
+int ntt_plan_create(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags, void* hip_stream) {
+  (void)hip_stream;
+  if (!out) return fail(NTT_EINVAL, "out is NULL");
+  *out = nullptr;
+  try {
+    int rc = create_plan(out, p, g, log2n, flags);
+    return rc ? rc : ok();
+  } catch (...) {
+    return fail(NTT_ENOMEM, "exception during plan creation");
+  }
+}
+
+int ntt_plan_destroy(ntt_plan* plan) {
+  if (!plan) return ok();
+  if (plan->dmem) (void)hipFree(plan->dmem);
+  delete plan;
+  return ok();
+}
+
+int ntt_plan_get_info(const ntt_plan* plan, ntt_plan_info* info) {
+  if (!plan || !info) return fail(NTT_EINVAL, "NULL argument");
+  info->p = plan->p;
+  info->g = plan->g;
+  info->w = plan->w;
+  info->w_inv = plan->winv;
+  info->n_inv = plan->ninv;
+  info->log2n = plan->log2n;
+  info->word_bits = plan->wbits;
+  info->flags = plan->flags;
+  info->passes = plan->passes;
+  return ok();
+}
+
+size_t ntt_workspace_bytes(const ntt_plan* plan, size_t batch) {
+  if (!plan || plan->passes == 1) return 0;
+  const bool natural_any = !(plan->flags & NTT_BITREV_OUT) || !(plan->flags & NTT_BITREV_IN);
+  if (!natural_any) return 0;
+  return ((size_t)1 << plan->log2n) * (plan->wbits / 8) * batch;
+}
+
+int ntt_forward(const ntt_plan* plan, const void* in, void* out, size_t batch, size_t stride_elems, void* workspace,
+                size_t ws_bytes, void* hip_stream) {
+  try {
+    return run_transform(plan, false, in, out, batch, stride_elems, workspace, ws_bytes, (hipStream_t)hip_stream);
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in ntt_forward");
+  }
+}
+
+int ntt_inverse(const ntt_plan* plan, const void* in, void* out, size_t batch, size_t stride_elems, void* workspace,
+                size_t ws_bytes, void* hip_stream) {
+  try {
+    return run_transform(plan, true, in, out, batch, stride_elems, workspace, ws_bytes, (hipStream_t)hip_stream);
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in ntt_inverse");
+  }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- products
+namespace {
+
+struct ProductShape {
+  uint64_t p;
+  int wb;       // word bits
+  int L;        // log2 of the transform length
+  bool fused;   // one workgroup per product
+  size_t lc;
+};
+
+int shape_of(uint64_t p, size_t la, size_t lb, ProductShape* s) {
+  int l = 0;
+  int rc = check_modulus(p, &l);
+  if (rc) return rc;
+  s->p = p;
+  s->wb = p < (1ull << 31) ? 32 : 64;
+  s->lc = la + lb - 1;
+  s->L = ceil_log2(s->lc);
+  if (s->L > l)
+    return fail(NTT_ENOROOT, "product length %zu needs 2^%d | p - 1 (2-adic order %d)", s->lc, s->L, l);
+  if (s->L > 26) return fail(NTT_EUNSUPPORTED, "product length %zu too large", s->lc);
+  s->fused = s->L <= fused_max_log2n(s->wb);
+  return NTT_OK;
+}
+
+size_t multipass_product_ws(const ProductShape& s) { return s.fused ? 0 : 2 * align256(((size_t)1 << s.L) * (s.wb / 8)); }
+
+// Two-pass product of one pair (section 5.2 with Algorithm 1): column passes of
+// both operands, the fused row pass, and the inverse column pass into c.
+int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const void* b, size_t lb, void* c, size_t lc,
+                          bool u16_inputs, void* ws, hipStream_t stream) {
+  const int wb = (int)pl->wbits;
+  const size_t N = (size_t)1 << pl->log2n;
+  unsigned char* w = (unsigned char*)ws;
+  void* A = w;
+  void* B = w + align256(N * (wb / 8));
+  PassArgs x;
+  memset(&x, 0, sizeof(x));
+  x.pc = pl->passc;
+  x.tw = pl->tw;
+  x.twi = pl->twi;
+  x.tlo = pl->tlo;
+  x.thi = pl->thi;
+  x.tilo = pl->tilo;
+  x.tihi = pl->tihi;  // no n^-1: the Montgomery scale folded into b carries it
+  x.batch = 1;
+  x.in_u16 = u16_inputs ? 1 : 0;
+  const int L1 = (int)pl->L1, L2 = (int)pl->L2;
+  x.in = a;
+  x.out = A;
+  x.valid = la;
+  x.scale = 0;
+  HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
+  x.in = b;
+  x.out = B;
+  x.valid = lb;
+  x.scale = 1;
+  HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
+  x.in_u16 = 0;
+  x.scale = 0;
+  x.in = A;
+  x.in2 = B;
+  x.out = A;
+  HIP_TRY(launch_row_polymul(wb, x, L1, L2, stream));
+  x.in = A;
+  x.out = c;
+  x.valid = lc;
+  HIP_TRY(launch_col_inv(wb, x, L1, L2, stream));
+  return NTT_OK;
+}
+
+FusedItem fused_item(const ntt_plan* pl, const void* a, size_t la, const void* b, size_t lb, void* c) {
+  FusedItem it;
+  memset(&it, 0, sizeof(it));
+  it.a = a;
+  it.b = b;
+  it.c = c;
+  it.la = la;
+  it.lb = lb;
+  it.cst = pl->polyc;
+  it.tw = pl->tw;
+  it.twi = pl->twi;
+  it.log2n = pl->log2n;
+  return it;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
+  if (la == 0 || lb == 0) return 0;
+  ProductShape s;
+  if (shape_of(p, la, lb, &s)) return 0;
+  return multipass_product_ws(s);
+}
+
+int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
+                 size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (la == 0 || lb == 0) return ok();
+    if (!a || !b || !c) return fail(NTT_EINVAL, "NULL operand pointer");
+    ProductShape s;
+    int rc = shape_of(p, la, lb, &s);
+    if (rc) return rc;
+    const size_t esz = s.wb / 8;
+    if (!aligned_to(a, esz) || !aligned_to(b, esz) || !aligned_to(c, esz))
+      return fail(NTT_EINVAL, "operands must be %zu-byte aligned", esz);
+    const size_t need = multipass_product_ws(s);
+    if (ws_bytes < need || (need && !workspace))
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    ntt_plan* pl = nullptr;
+    rc = cached_plan(p, (uint32_t)s.L, &pl);
+    if (rc) return rc;
+    if (s.fused) {
+      FusedBatch fb;
+      memset(&fb, 0, sizeof(fb));
+      fb.items = nullptr;
+      fb.count = 1;
+      fb.single = fused_item(pl, a, la, b, lb, c);
+      HIP_TRY(launch_fused(s.wb, fused_class(s.wb, s.L), fb, 1, stream));
+      return ok();
+    }
+    rc = run_multipass_product(pl, a, la, b, lb, c, s.lc, false, workspace, stream);
+    return rc ? rc : ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymul_modp");
+  }
+}
+
+size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count) {
+  if (!d && count) return 0;
+  size_t items = 0, big = 0;
+  for (size_t i = 0; i < count; ++i) {
+    if (d[i].la == 0 || d[i].lb == 0) continue;
+    ProductShape s;
+    if (shape_of(d[i].p, d[i].la, d[i].lb, &s)) continue;
+    if (s.fused) ++items;
+    else big = std::max(big, multipass_product_ws(s));
+  }
+  return align256(items * sizeof(FusedItem)) + big;
+}
+
+int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (count == 0) return ok();
+    if (!d) return fail(NTT_EINVAL, "descriptor array is NULL");
+    std::vector<ProductShape> shapes(count);
+    size_t nfused = 0, big = 0;
+    for (size_t i = 0; i < count; ++i) {
+      if (d[i].la == 0 || d[i].lb == 0) {
+        shapes[i].L = -1;
+        continue;
+      }
+      if (!d[i].a || !d[i].b || !d[i].c) return fail(NTT_EINVAL, "descriptor %zu: NULL operand pointer", i);
+      int rc = shape_of(d[i].p, d[i].la, d[i].lb, &shapes[i]);
+      if (rc) {
+        std::string m = g_last_error;
+        return fail(rc, "descriptor %zu: %s", i, m.c_str());
+      }
+      const size_t esz = shapes[i].wb / 8;
+      if (!aligned_to(d[i].a, esz) || !aligned_to(d[i].b, esz) || !aligned_to(d[i].c, esz))
+        return fail(NTT_EINVAL, "descriptor %zu: operands must be %zu-byte aligned", i, esz);
+      if (shapes[i].fused) ++nfused;
+      else big = std::max(big, multipass_product_ws(shapes[i]));
+    }
+    const size_t need = align256(nfused * sizeof(FusedItem)) + big;
+    if (ws_bytes < need || (need && !workspace))
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    DeviceCtx* ctx = device_ctx(dev);
+    // Group the fused items by (word size, size class), in one contiguous upload.
+    std::vector<FusedItem> items;
+    items.reserve(nfused);
+    struct Group { int wb, cls; size_t first, count; };
+    std::vector<Group> groups;
+    for (int wb : {32, 64}) {
+      for (int cls = 0; cls < 4; ++cls) {
+        const size_t first = items.size();
+        for (size_t i = 0; i < count; ++i) {
+          const ProductShape& s = shapes[i];
+          if (s.L < 0 || !s.fused || s.wb != wb || fused_class(wb, s.L) != cls) continue;
+          ntt_plan* pl = nullptr;
+          int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
+          if (rc) return rc;
+          items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+        }
+        if (items.size() > first) groups.push_back({wb, cls, first, items.size() - first});
+      }
+    }
+    FusedItem* ditems = (FusedItem*)workspace;
+    if (!items.empty()) {
+      int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
+      if (rc) return rc;
+    }
+    for (const Group& g : groups) {
+      FusedBatch fb;
+      memset(&fb, 0, sizeof(fb));
+      fb.items = ditems + g.first;
+      fb.count = (int)g.count;
+      const int grid = (int)std::min<size_t>(g.count, 1u << 20);
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, grid, stream));
+    }
+    void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
+    for (size_t i = 0; i < count; ++i) {
+      const ProductShape& s = shapes[i];
+      if (s.L < 0 || s.fused) continue;
+      ntt_plan* pl = nullptr;
+      int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
+      if (rc) return rc;
+      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, bigws, stream);
+      if (rc) return rc;
+    }
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymul_modp_batch");
+  }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- integer product
+namespace {
+
+const uint32_t kIntPrimes[3] = {998244353u, 469762049u, 167772161u};
+const size_t kIntMaxCoeffs = (size_t)1 << 23;
+
+struct IntLayout {
+  size_t lc, npos, N, nblk;
+  int L;
+  bool fused;
+  size_t o_r[3], o_t, o_blk, o_a32, o_b32, o_big, total;
+};
+
+IntLayout int_layout(size_t na, size_t nb) {
+  IntLayout z;
+  memset(&z, 0, sizeof(z));
+  z.lc = na + nb - 1;
+  z.L = ceil_log2(z.lc);
+  z.N = (size_t)1 << z.L;
+  z.npos = (na + nb + 1) & ~(size_t)1;
+  z.nblk = (z.npos + crt_block_positions() - 1) / crt_block_positions();
+  z.fused = z.L <= fused_max_log2n(32);
+  size_t off = 0;
+  for (int i = 0; i < 3; ++i) {
+    z.o_r[i] = off;
+    off += align256(z.lc * 4);
+  }
+  z.o_t = off;
+  off += align256(z.npos * 4);
+  z.o_blk = off;
+  off += align256(z.nblk * 4);
+  if (z.fused) {
+    z.o_a32 = off;
+    off += align256(na * 4);
+    z.o_b32 = off;
+    off += align256(nb * 4);
+  } else {
+    z.o_big = off;
+    off += 2 * align256(z.N * 4);
+  }
+  z.total = off;
+  return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t intmul_workspace_bytes(size_t na, size_t nb) {
+  if (na == 0 || nb == 0) return 0;
+  if (na + nb - 1 > kIntMaxCoeffs) return 0;
+  return int_layout(na, nb).total;
+}
+
+int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint32_t* c, void* workspace,
+               size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const size_t nc32 = (na + nb + 1) / 2;
+    if (nc32 && !c) return fail(NTT_EINVAL, "output pointer is NULL");
+    if (!aligned_to(c, 4) || !aligned_to(a, 2) || !aligned_to(b, 2)) return fail(NTT_EINVAL, "misaligned pointer");
+    if (na == 0 || nb == 0) {
+      HIP_TRY(launch_fill_u32(c, nc32, 0u, stream));
+      return ok();
+    }
+    if (!a || !b) return fail(NTT_EINVAL, "NULL operand pointer");
+    if (na + nb - 1 > kIntMaxCoeffs)
+      return fail(NTT_EINVAL, "na + nb - 1 = %zu exceeds 2^23 coefficients", na + nb - 1);
+    const IntLayout z = int_layout(na, nb);
+    if (ws_bytes < z.total || !workspace)
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", z.total, ws_bytes);
+    unsigned char* w = (unsigned char*)workspace;
+    uint32_t* r[3];
+    for (int i = 0; i < 3; ++i) r[i] = (uint32_t*)(w + z.o_r[i]);
+    const void* a_in = a;
+    const void* b_in = b;
+    if (z.fused) {
+      uint32_t* a32 = (uint32_t*)(w + z.o_a32);
+      uint32_t* b32 = (uint32_t*)(w + z.o_b32);
+      HIP_TRY(launch_widen_u16(a, a32, na, stream));
+      HIP_TRY(launch_widen_u16(b, b32, nb, stream));
+      a_in = a32;
+      b_in = b32;
+    }
+    for (int i = 0; i < 3; ++i) {
+      ntt_plan* pl = nullptr;
+      int rc = cached_plan(kIntPrimes[i], (uint32_t)z.L, &pl);
+      if (rc) return rc;
+      if (z.fused) {
+        FusedBatch fb;
+        memset(&fb, 0, sizeof(fb));
+        fb.count = 1;
+        fb.single = fused_item(pl, a_in, na, b_in, nb, r[i]);
+        HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
+      } else {
+        rc = run_multipass_product(pl, a, na, b, nb, r[i], z.lc, true, w + z.o_big, stream);
+        if (rc) return rc;
+      }
+    }
+    CrtArgs x;
+    memset(&x, 0, sizeof(x));
+    x.r1 = r[0];
+    x.r2 = r[1];
+    x.r3 = r[2];
+    x.lc = z.lc;
+    x.npos = z.npos;
+    x.t = (uint32_t*)(w + z.o_t);
+    x.blk = (uint32_t*)(w + z.o_blk);
+    x.c = c;
+    const uint64_t p1 = kIntPrimes[0], p2 = kIntPrimes[1], p3 = kIntPrimes[2];
+    x.p1 = (uint32_t)p1;
+    x.p2 = (uint32_t)p2;
+    x.p3 = (uint32_t)p3;
+    const uint64_t c12 = invmod(p1 % p2, p2);
+    const uint64_t c123 = invmod(mulmod(p1 % p3, p2 % p3, p3), p3);
+    x.c12 = (uint32_t)c12;
+    x.c12s = (uint32_t)((c12 << 32) / p2);
+    x.c123 = (uint32_t)c123;
+    x.c123s = (uint32_t)((c123 << 32) / p3);
+    x.p1m3 = (uint32_t)(p1 % p3);
+    x.p1m3s = (uint32_t)(((p1 % p3) << 32) / p3);
+    x.p1p2 = p1 * p2;
+    HIP_TRY(launch_crt_carry(x, stream));
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in intmul_crt");
+  }
+}
+
+}  // extern "C"

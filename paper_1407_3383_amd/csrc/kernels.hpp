@@ -1,0 +1,99 @@
+// Kernel launch interface used by the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+#include "ntt_lds.hpp"
+
+namespace nttgpu {
+
+struct FusedBatch {
+  const FusedItem* items;  // device array, or NULL to use `single`
+  int count;
+  int pad;
+  FusedItem single;
+};
+
+int fused_class(int word_bits, int log2n);
+int fused_max_log2n(int word_bits);
+hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int grid, hipStream_t stream);
+
+// Transform of `batch` vectors that fit one workgroup's LDS (log2n <= lds_max_log2n).
+struct LdsNttArgs {
+  const void* in;
+  void* out;
+  uint64_t stride;  // elements between vectors
+  const void* pc;   // PassConst<T>
+  const void* tw;   // universal tables
+  const void* twi;
+  uint32_t L;
+  uint32_t bitrev;  // forward: leave TFT order; inverse: input in TFT order
+  uint32_t batch;
+  uint32_t pad;
+};
+int lds_max_log2n(int word_bits);
+hipError_t launch_lds_ntt(int word_bits, bool inverse, const LdsNttArgs& a, hipStream_t stream);
+
+// Two-pass transform (section 5.1, Algorithm 1 with n1 = 2^L1 columns of the
+// row-major 2^L1 x 2^L2 layout and rows of length 2^L2).
+struct PassArgs {
+  const void* in;   // pass input (column forward pass: may be uint16_t limbs)
+  void* out;        // pass output
+  const void* in2;  // second operand (fused product row pass)
+  uint64_t in_stride, out_stride;  // elements between batch vectors
+  uint64_t valid;   // column forward pass: input elements at index >= valid read as 0
+  const void* pc;   // PassConst<T>
+  const void* tw;   // universal tables (stages of the column pass / the row transform)
+  const void* twi;
+  const void* tlo;  // two-level twist tables (forward, inverse, inverse * n^-1)
+  const void* thi;
+  const void* tilo;
+  const void* tihi;
+  uint32_t batch;
+  uint32_t scale;   // column forward pass: multiply inputs by sigma (second operand of a product)
+  uint32_t in_u16;  // column forward pass: input is 16-bit limbs
+  uint32_t pad;
+};
+hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool scale_ninv, hipStream_t stream);
+hipError_t launch_row_polymul(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+int pass_max_row_log2(int word_bits);
+int pass_col_tile_log2(int word_bits);
+
+// out[i] = in[[i]_L] for `batch` vectors of 2^L elements (bit-reversal permutation).
+hipError_t launch_bitrev_permute(int word_bits, const void* in, void* out, uint64_t in_stride, uint64_t out_stride,
+                                 uint32_t L, uint32_t batch, hipStream_t stream);
+
+// x[0 .. n) = value.
+hipError_t launch_fill_u32(uint32_t* x, uint64_t n, uint32_t value, hipStream_t stream);
+
+// u16 limbs -> u32 residues (every prime of the integer product exceeds 2^16).
+hipError_t launch_widen_u16(const uint16_t* in, uint32_t* out, uint64_t n, hipStream_t stream);
+
+// Element-wise checks for NTT_VALIDATE: sets *flag to 1 if any element >= p.
+hipError_t launch_range_check(int word_bits, const void* x, uint64_t n, uint64_t stride, uint32_t batch, uint64_t p,
+                              uint32_t* flag, hipStream_t stream);
+
+// Integer product: Garner reconstruction + carry propagation into 32-bit limbs.
+struct CrtArgs {
+  const uint32_t* r1;
+  const uint32_t* r2;
+  const uint32_t* r3;
+  uint64_t lc;       // number of coefficients (na + nb - 1)
+  uint64_t npos;     // number of 16-bit output positions (na + nb), even-padded
+  uint32_t* t;       // workspace: npos column sums with one level of carry applied
+  uint32_t* blk;     // workspace: per-block (generate, propagate) then carry-in
+  uint32_t* c;       // output: npos / 2 limbs of 32 bits
+  uint32_t p1, p2, p3;
+  uint32_t c12, c12s;    // p1^-1 mod p2 and its Shoup companion
+  uint32_t c123, c123s;  // (p1 p2)^-1 mod p3 and companion
+  uint32_t p1m3, p1m3s;  // p1 mod p3 and companion
+  uint64_t p1p2;
+};
+int crt_block_positions();
+hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream);
+
+}  // namespace nttgpu

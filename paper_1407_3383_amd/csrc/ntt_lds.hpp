@@ -1,0 +1,236 @@
+// Workgroup-level transforms of a vector resident in LDS (section 5.1).
+//
+// The forward transform is the in-place Cooley-Tukey form that takes natural order
+// to bit-reversed (TFT) order; the inverse is the Gentleman-Sande form that takes
+// bit-reversed order back to natural order.  Stage s of a length-2^L transform
+// pairs indices that differ in bit L-1-s; the pair in block i (the top s bits of
+// the index) uses the universal bit-reversed table
+//     TW[2^s + i] = w_{2^(s+1)}^([i]_s),  w_{2^j} = g^((p-1)/2^j),
+// which does not depend on L, so one table serves every length.
+//
+// A vector held in LDS may be a sub-problem: block h (of size 2^m) at depth d of a
+// length-2^(d+m) transform.  Its stages are the global stages d .. d+m-1 and the
+// table index of local block b at local stage t is 2^(d+t) + (h << t) + b.  This is
+// Algorithm 1's split (n1 = 2^d vectors of length 2^m) with the twiddle step of its
+// step 2 folded into the table.
+//
+// Threads work on radix-2^R clusters: 2^R elements at stride 2^(m-t0-R) that stay
+// together for R consecutive stages t0 .. t0+R-1, so one LDS round trip serves R
+// stages.  LDS indices are padded (one word per 32) against bank conflicts.
+#pragma once
+#include "arith.hpp"
+
+namespace nttgpu {
+
+__device__ __forceinline__ int lidx(int e) { return e + (e >> 5); }
+__host__ __device__ constexpr int lds_words(int n) { return n + (n >> 5); }
+
+template <typename T, bool LAZY, int R, int NT, bool TWO>
+__device__ __forceinline__ void fwd_round(const Arith<T>& ar, T* sa, T* sb, int m, int t0, int d, uint32_t h,
+                                          const TwPair<T>* __restrict__ tw) {
+  constexpr int C = 1 << R;
+  const int ls = m - t0 - R;  // log2 of the element stride inside a cluster
+  const int nclust = 1 << (m - R);
+  for (int q = threadIdx.x; q < nclust; q += NT) {
+    const int b = q >> ls;
+    const int base = (b << (m - t0)) + (q & ((1 << ls) - 1));
+    T xa[C], xb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      xa[c] = sa[lidx(base + (c << ls))];
+      if constexpr (TWO) xb[c] = sb[lidx(base + (c << ls))];
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int s = d + t0 + u;
+      const int half = 1 << (R - 1 - u);
+      const uint32_t blk0 = (1u << s) + (h << (t0 + u)) + ((uint32_t)b << u);
+#pragma unroll
+      for (int v = 0; v < (1 << u); ++v) {
+        const TwPair<T> w = tw[blk0 + v];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (v << (R - u)) + c2;
+          ct_bfly<LAZY>(ar, xa[c], xa[c + half], w);
+          if constexpr (TWO) ct_bfly<LAZY>(ar, xb[c], xb[c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      sa[lidx(base + (c << ls))] = xa[c];
+      if constexpr (TWO) sb[lidx(base + (c << ls))] = xb[c];
+    }
+  }
+}
+
+template <typename T, bool LAZY, int R, int NT>
+__device__ __forceinline__ void inv_round(const Arith<T>& ar, T* sa, int m, int t0, int d, uint32_t h,
+                                          const TwPair<T>* __restrict__ twi) {
+  constexpr int C = 1 << R;
+  const int ls = m - t0 - R;
+  const int nclust = 1 << (m - R);
+  for (int q = threadIdx.x; q < nclust; q += NT) {
+    const int b = q >> ls;
+    const int base = (b << (m - t0)) + (q & ((1 << ls) - 1));
+    T x[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = sa[lidx(base + (c << ls))];
+#pragma unroll
+    for (int u = R - 1; u >= 0; --u) {
+      const int s = d + t0 + u;
+      const int half = 1 << (R - 1 - u);
+      const uint32_t blk0 = (1u << s) + (h << (t0 + u)) + ((uint32_t)b << u);
+#pragma unroll
+      for (int v = 0; v < (1 << u); ++v) {
+        const TwPair<T> w = twi[blk0 + v];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (v << (R - u)) + c2;
+          gs_bfly<LAZY>(ar, x[c], x[c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[lidx(base + (c << ls))] = x[c];
+  }
+}
+
+// All m stages of the forward transform of the LDS vector(s); the first round takes
+// the m mod 4 leftover stages, the others radix 16.  Ends with a barrier.
+template <typename T, bool LAZY, int NT, bool TWO>
+__device__ void fwd_lds(const Arith<T>& ar, T* sa, T* sb, int m, int d, uint32_t h, const TwPair<T>* __restrict__ tw) {
+  int t0 = 0;
+  switch (m & 3) {
+    case 1: fwd_round<T, LAZY, 1, NT, TWO>(ar, sa, sb, m, 0, d, h, tw); t0 = 1; __syncthreads(); break;
+    case 2: fwd_round<T, LAZY, 2, NT, TWO>(ar, sa, sb, m, 0, d, h, tw); t0 = 2; __syncthreads(); break;
+    case 3: fwd_round<T, LAZY, 3, NT, TWO>(ar, sa, sb, m, 0, d, h, tw); t0 = 3; __syncthreads(); break;
+    default: break;
+  }
+  for (; t0 < m; t0 += 4) {
+    fwd_round<T, LAZY, 4, NT, TWO>(ar, sa, sb, m, t0, d, h, tw);
+    __syncthreads();
+  }
+}
+
+// Inverse of fwd_lds's stage sequence (rounds in reverse order).  Ends with a barrier.
+template <typename T, bool LAZY, int NT>
+__device__ void inv_lds(const Arith<T>& ar, T* sa, int m, int d, uint32_t h, const TwPair<T>* __restrict__ twi) {
+  const int r0 = m & 3;
+  for (int t0 = m - 4; t0 >= r0; t0 -= 4) {
+    inv_round<T, LAZY, 4, NT>(ar, sa, m, t0, d, h, twi);
+    __syncthreads();
+  }
+  switch (r0) {
+    case 1: inv_round<T, LAZY, 1, NT>(ar, sa, m, 0, d, h, twi); __syncthreads(); break;
+    case 2: inv_round<T, LAZY, 2, NT>(ar, sa, m, 0, d, h, twi); __syncthreads(); break;
+    case 3: inv_round<T, LAZY, 3, NT>(ar, sa, m, 0, d, h, twi); __syncthreads(); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The same stage sequence on `nvec` independent vectors of length 2^m stored at
+// LDS offsets v * vs (plain transforms: depth 0, block 0).  Work items are
+// (vector, cluster) pairs spread over the workgroup.
+template <typename T, bool LAZY, int R, int NT>
+__device__ __forceinline__ void fwd_round_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, int t0,
+                                                const TwPair<T>* __restrict__ tw) {
+  constexpr int C = 1 << R;
+  const int ls = m - t0 - R;
+  const int lcl = m - R;  // log2 clusters per vector
+  const int nitems = nvec << lcl;
+  for (int q = threadIdx.x; q < nitems; q += NT) {
+    T* sv = s + (q >> lcl) * vs;
+    const int qc = q & ((1 << lcl) - 1);
+    const int b = qc >> ls;
+    const int base = (b << (m - t0)) + (qc & ((1 << ls) - 1));
+    T x[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = sv[lidx(base + (c << ls))];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int st = t0 + u;
+      const int half = 1 << (R - 1 - u);
+      const uint32_t blk0 = (1u << st) + ((uint32_t)b << u);
+#pragma unroll
+      for (int v = 0; v < (1 << u); ++v) {
+        const TwPair<T> w = tw[blk0 + v];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (v << (R - u)) + c2;
+          ct_bfly<LAZY>(ar, x[c], x[c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sv[lidx(base + (c << ls))] = x[c];
+  }
+}
+
+template <typename T, bool LAZY, int R, int NT>
+__device__ __forceinline__ void inv_round_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, int t0,
+                                                const TwPair<T>* __restrict__ twi) {
+  constexpr int C = 1 << R;
+  const int ls = m - t0 - R;
+  const int lcl = m - R;
+  const int nitems = nvec << lcl;
+  for (int q = threadIdx.x; q < nitems; q += NT) {
+    T* sv = s + (q >> lcl) * vs;
+    const int qc = q & ((1 << lcl) - 1);
+    const int b = qc >> ls;
+    const int base = (b << (m - t0)) + (qc & ((1 << ls) - 1));
+    T x[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = sv[lidx(base + (c << ls))];
+#pragma unroll
+    for (int u = R - 1; u >= 0; --u) {
+      const int st = t0 + u;
+      const int half = 1 << (R - 1 - u);
+      const uint32_t blk0 = (1u << st) + ((uint32_t)b << u);
+#pragma unroll
+      for (int v = 0; v < (1 << u); ++v) {
+        const TwPair<T> w = twi[blk0 + v];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (v << (R - u)) + c2;
+          gs_bfly<LAZY>(ar, x[c], x[c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sv[lidx(base + (c << ls))] = x[c];
+  }
+}
+
+template <typename T, bool LAZY, int NT>
+__device__ void fwd_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, const TwPair<T>* __restrict__ tw) {
+  int t0 = 0;
+  switch (m & 3) {
+    case 1: fwd_round_multi<T, LAZY, 1, NT>(ar, s, vs, nvec, m, 0, tw); t0 = 1; __syncthreads(); break;
+    case 2: fwd_round_multi<T, LAZY, 2, NT>(ar, s, vs, nvec, m, 0, tw); t0 = 2; __syncthreads(); break;
+    case 3: fwd_round_multi<T, LAZY, 3, NT>(ar, s, vs, nvec, m, 0, tw); t0 = 3; __syncthreads(); break;
+    default: break;
+  }
+  for (; t0 < m; t0 += 4) {
+    fwd_round_multi<T, LAZY, 4, NT>(ar, s, vs, nvec, m, t0, tw);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool LAZY, int NT>
+__device__ void inv_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, const TwPair<T>* __restrict__ twi) {
+  const int r0 = m & 3;
+  for (int t0 = m - 4; t0 >= r0; t0 -= 4) {
+    inv_round_multi<T, LAZY, 4, NT>(ar, s, vs, nvec, m, t0, twi);
+    __syncthreads();
+  }
+  switch (r0) {
+    case 1: inv_round_multi<T, LAZY, 1, NT>(ar, s, vs, nvec, m, 0, twi); __syncthreads(); break;
+    case 2: inv_round_multi<T, LAZY, 2, NT>(ar, s, vs, nvec, m, 0, twi); __syncthreads(); break;
+    case 3: inv_round_multi<T, LAZY, 3, NT>(ar, s, vs, nvec, m, 0, twi); __syncthreads(); break;
+    default: break;
+  }
+}
+
+}  // namespace nttgpu

