@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched polynomial product mod p on one MI355X.
+
+Workload: 1024 independent products mod p = 2013265921 (15 * 2^27 + 1), both operands
+of length 2^15 with uniform residues, transform length 2^16 (section 5.2's product:
+two forward transforms, entry-wise product, one inverse), all in one fused launch.
+A step is one such batched launch with the operands already resident in HBM.
+
+Printed (one JSON line): radix-2-equivalent butterflies per second over the three
+transforms of every product, the HBM traffic rate on algorithmic bytes, the roofline
+of the fused kernel (it is bound by the integer VALU), the same products issued as
+1024 separate per-call launches, and the CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "NTT polymul mod p: Gbutterflies/s, % HBM roofline, batched vs per-call"
+P = 2013265921
+HBM_PEAK_GBPS = 8000.0
+# Integer-VALU peak: 256 CUs x 64 lanes x 2.4 GHz of 32-bit lane operations (the
+# 32-bit multiplies issue at the same rate as adds and mins on gfx950).
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# Algorithmic integer operations of one radix-2 butterfly with a precomputed-
+# multiplicand twiddle: 3 multiplies + 1 subtraction (Function 8 without the final
+# correction) and 5 add/sub/min for the lazy sum and difference.
+OPS_PER_BFLY = 9
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--items", type=int, default=1024)
+    ap.add_argument("--log2len", type=int, default=15)
+    ap.add_argument("--percall-steps", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-percall", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the products shard trivially across GPUs; see the design notes).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt
+
+    torch.cuda.set_device(0)
+    items, L = args.items, 1 << args.log2len
+    lc = 2 * L - 1
+    log2N = (lc - 1).bit_length()
+    N = 1 << log2N
+    bfly_per_item = 3 * (N // 2) * log2N
+    bfly_per_step = items * bfly_per_item
+    alg_bytes = items * (2 * L * 4 + lc * 4)
+
+    log("generating %d x 2 operands of length %d" % (items, L))
+    _, A, B = inputs.polymul_batch_inputs(items, L, P)
+    dA, dB = ntt.to_device(A), ntt.to_device(B)
+    dC = torch.empty((items, lc), dtype=torch.int32, device="cuda")
+    batch = ntt.Batch.rows(dA, dB, dC, P)
+    stream = torch.cuda.Stream()
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        batch(stream)
+    torch.cuda.synchronize()
+
+    log("timing %d steps" % args.steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        batch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = e0.elapsed_time(e1) / args.steps  # one fused kernel per step
+    ms_per_step = wall * 1e3 / args.steps
+    value = bfly_per_step / (ms_per_step * 1e-3) / 1e9
+    log("batched: %.3f ms/step (events %.3f ms/kernel), %.1f Gbfly/s" % (ms_per_step, kern_ms, value))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gbfly/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched polymul: %d products mod %d, operands of length %d, transform length %d, one fused launch"
+                        % (items, P, L, N),
+            "items": items, "operand_len": L, "ntt_len": N, "p": P,
+        },
+        "hbm": {
+            "algorithmic_bytes_per_step": alg_bytes,
+            "achieved_GBps": round(alg_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+            "peak_GBps": HBM_PEAK_GBPS,
+            "frac": round(alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        },
+    }
+    achieved_tops = bfly_per_step * OPS_PER_BFLY / (kern_ms * 1e-3) / 1e12
+    out["roofline"] = {
+        "bound": "alu",
+        "kernel": "polymul_fused_kernel<u32, 1024 threads, 2^14-word sub-problems>",
+        "achieved": round(achieved_tops, 3),
+        "peak": round(ALU_PEAK_TOPS, 3),
+        "unit": "Tops/s (32-bit integer lane operations, %d per butterfly)" % OPS_PER_BFLY,
+        "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
+        "traffic": None,
+        "kernel_ms": round(kern_ms, 4),
+    }
+
+    if not args.no_percall:
+        log("per-call baseline: %d separate polymul_modp launches x %d steps" % (items, args.percall_steps))
+        rows = [(dA[i], dB[i], dC[i]) for i in range(items)]
+        with torch.cuda.stream(stream):
+            for a, b, c in rows[:8]:
+                ntt.polymul(a, b, P, out=c, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(args.percall_steps):
+                for a, b, c in rows:
+                    ntt.polymul(a, b, P, out=c, stream=stream)
+        torch.cuda.synchronize()
+        pc_ms = (time.perf_counter() - t0) * 1e3 / args.percall_steps
+        out["per_call"] = {
+            "ms_per_step": round(pc_ms, 3),
+            "value": round(bfly_per_step / (pc_ms * 1e-3) / 1e9, 3),
+            "unit": "Gbfly/s",
+            "batched_speedup": round(pc_ms / ms_per_step, 2),
+            "how": "the same %d products as %d polymul_modp calls on one stream" % (items, items),
+        }
+        log("per-call: %.2f ms/step" % pc_ms)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("cpu baseline: oracle transform product on sampled items for ~%.0f s" % args.cpu_seconds)
+        C = ntt.to_numpy(dC)
+        done, t0 = 0, time.perf_counter()
+        mismatches = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and done < items:
+            i = (done * 97) % items
+            ref = oracle.polymul_ntt(A[i], B[i], P, 31)
+            mismatches += int(not np.array_equal(ref, C[i].astype(np.uint64)))
+            done += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(done * bfly_per_item / el / 1e9, 6),
+            "unit": "Gbfly/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": "%d of the %d products (textbook radix-2 transforms, __int128 %% reductions), %.1f s" % (done, items, el),
+            "gpu_vs_oracle_mismatches": mismatches,
+        }
+        if mismatches:
+            log("WARNING: %d sampled products differ from the oracle" % mismatches)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

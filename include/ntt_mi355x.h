@@ -158,6 +158,20 @@ size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
 int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes,
                        void* hip_stream);
 
+/* Reusable batch: the descriptors are checked, their plans created and their
+ * device form uploaded once (synchronously) into device memory the handle owns;
+ * every launch then only enqueues kernels on `hip_stream` (nothing is copied or
+ * allocated), so a launch can be repeated, overlapped on several streams when the
+ * operands differ, or captured in a HIP graph.  The operand pointers are bound at
+ * creation.  Errors as polymul_modp_batch. */
+typedef struct ntt_batch ntt_batch;
+int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t count);
+/* Device scratch needed by polymul_batch_launch (0 when every product is fused). */
+size_t polymul_batch_launch_workspace_bytes(const ntt_batch* batch);
+int polymul_batch_launch(const ntt_batch* batch, void* workspace, size_t ws_bytes, void* hip_stream);
+/* NULL is accepted; the caller makes sure no launch of the batch is still pending. */
+int polymul_batch_destroy(ntt_batch* batch);
+
 /* ---------------------------------------------------------------- integer product
  * Section 5.3: Kronecker segmentation with 16-bit chunks (A(2^16) = a) and the
  * three-prime transform over p1 = 998244353, p2 = 469762049, p3 = 167772161,

@@ -907,6 +907,131 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------- reusable batches
+struct ntt_batch {
+  int device;
+  void* ditems;  // device FusedItem array (owned)
+  struct Group { int wb, cls; size_t first, count; };
+  std::vector<Group> groups;
+  struct Big { const ntt_plan* pl; const void *a, *b; void* c; size_t la, lb, lc; };
+  std::vector<Big> big;
+  size_t big_ws;
+};
+
+extern "C" {
+
+int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t count) {
+  try {
+    if (!out) return fail(NTT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count && !d) return fail(NTT_EINVAL, "descriptor array is NULL");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<ProductShape> shapes(count);
+    for (size_t i = 0; i < count; ++i) {
+      if (d[i].la == 0 || d[i].lb == 0) {
+        shapes[i].L = -1;
+        continue;
+      }
+      if (!d[i].a || !d[i].b || !d[i].c) return fail(NTT_EINVAL, "descriptor %zu: NULL operand pointer", i);
+      int rc = shape_of(d[i].p, d[i].la, d[i].lb, &shapes[i]);
+      if (rc) {
+        std::string m = g_last_error;
+        return fail(rc, "descriptor %zu: %s", i, m.c_str());
+      }
+      const size_t esz = shapes[i].wb / 8;
+      if (!aligned_to(d[i].a, esz) || !aligned_to(d[i].b, esz) || !aligned_to(d[i].c, esz))
+        return fail(NTT_EINVAL, "descriptor %zu: operands must be %zu-byte aligned", i, esz);
+    }
+    ntt_batch* bt = new ntt_batch();
+    bt->device = dev;
+    bt->ditems = nullptr;
+    bt->big_ws = 0;
+    std::vector<FusedItem> items;
+    for (int wb : {32, 64}) {
+      for (int cls = 0; cls < 4; ++cls) {
+        const size_t first = items.size();
+        for (size_t i = 0; i < count; ++i) {
+          const ProductShape& s = shapes[i];
+          if (s.L < 0 || !s.fused || s.wb != wb || fused_class(wb, s.L) != cls) continue;
+          ntt_plan* pl = nullptr;
+          int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
+          if (rc) {
+            delete bt;
+            return rc;
+          }
+          items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+        }
+        if (items.size() > first) bt->groups.push_back({wb, cls, first, items.size() - first});
+      }
+    }
+    for (size_t i = 0; i < count; ++i) {
+      const ProductShape& s = shapes[i];
+      if (s.L < 0 || s.fused) continue;
+      ntt_plan* pl = nullptr;
+      int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
+      if (rc) {
+        delete bt;
+        return rc;
+      }
+      bt->big.push_back({pl, d[i].a, d[i].b, d[i].c, d[i].la, d[i].lb, s.lc});
+      bt->big_ws = std::max(bt->big_ws, multipass_product_ws(s));
+    }
+    if (!items.empty()) {
+      if (hipMalloc(&bt->ditems, items.size() * sizeof(FusedItem)) != hipSuccess) {
+        delete bt;
+        return fail(NTT_ENOMEM, "hipMalloc of batch descriptors failed");
+      }
+      if (hipMemcpy(bt->ditems, items.data(), items.size() * sizeof(FusedItem), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(bt->ditems);
+        delete bt;
+        return fail(NTT_EDEVICE, "upload of batch descriptors failed");
+      }
+    }
+    *out = bt;
+    return ok();
+  } catch (...) {
+    return fail(NTT_ENOMEM, "exception in polymul_batch_create");
+  }
+}
+
+size_t polymul_batch_launch_workspace_bytes(const ntt_batch* batch) { return batch ? batch->big_ws : 0; }
+
+int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, void* hip_stream) {
+  try {
+    if (!bt) return fail(NTT_EINVAL, "batch is NULL");
+    hipStream_t stream = (hipStream_t)hip_stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != bt->device) return fail(NTT_EINVAL, "batch belongs to device %d, current device is %d", bt->device, dev);
+    if (ws_bytes < bt->big_ws || (bt->big_ws && !workspace))
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", bt->big_ws, ws_bytes);
+    for (const auto& g : bt->groups) {
+      FusedBatch fb;
+      memset(&fb, 0, sizeof(fb));
+      fb.items = (const FusedItem*)bt->ditems + g.first;
+      fb.count = (int)g.count;
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, (int)std::min<size_t>(g.count, 1u << 20), stream));
+    }
+    for (const auto& b : bt->big) {
+      int rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, workspace, stream);
+      if (rc) return rc;
+    }
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymul_batch_launch");
+  }
+}
+
+int polymul_batch_destroy(ntt_batch* bt) {
+  if (!bt) return ok();
+  if (bt->ditems) (void)hipFree(bt->ditems);
+  delete bt;
+  return ok();
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------- integer product
 namespace {
 

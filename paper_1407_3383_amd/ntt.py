@@ -38,7 +38,9 @@ EXPORTS = (
     "ntt_strerror", "ntt_last_error", "ntt_is_prime", "ntt_smallest_generator", "ntt_find_prime",
     "ntt_plan_create", "ntt_plan_destroy", "ntt_plan_get_info", "ntt_workspace_bytes",
     "ntt_forward", "ntt_inverse", "polymul_workspace_bytes", "polymul_modp",
-    "polymul_batch_workspace_bytes", "polymul_modp_batch", "intmul_workspace_bytes", "intmul_crt",
+    "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
+    "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
+    "intmul_workspace_bytes", "intmul_crt",
 )
 
 
@@ -87,6 +89,10 @@ def load(path: str = LIB_PATH):
         "polymul_modp": (ci, [u64, vp, sz, vp, sz, vp, vp, sz, vp]),
         "polymul_batch_workspace_bytes": (sz, [ctypes.POINTER(PolymulDesc), sz]),
         "polymul_modp_batch": (ci, [ctypes.POINTER(PolymulDesc), sz, vp, sz, vp]),
+        "polymul_batch_create": (ci, [ctypes.POINTER(vp), ctypes.POINTER(PolymulDesc), sz]),
+        "polymul_batch_launch_workspace_bytes": (sz, [vp]),
+        "polymul_batch_launch": (ci, [vp, vp, sz, vp]),
+        "polymul_batch_destroy": (ci, [vp]),
         "intmul_workspace_bytes": (sz, [sz, sz]),
         "intmul_crt": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
     }
@@ -232,27 +238,62 @@ def polymul_rows(A, B, p: int, out=None, stream=None, workspace=None):
     return out
 
 
-class BatchLauncher:
-    """Pre-marshalled batched product over fixed buffers (descriptors built once)."""
+class Batch:
+    """Reusable batch handle (polymul_batch_create): descriptors live on the device;
+    each call only launches kernels, so it can be repeated or graph-captured."""
 
-    def __init__(self, A, B, out, p: int):
+    def __init__(self, pairs_or_descs, primes=None, outs=None):
         L = load()
+        if primes is not None:
+            descs = (PolymulDesc * max(len(pairs_or_descs), 1))()
+            for i, ((a, b), p) in enumerate(zip(pairs_or_descs, primes)):
+                descs[i] = PolymulDesc(p, _ptr(a).value, a.numel(), _ptr(b).value, b.numel(), _ptr(outs[i]).value)
+            count = len(pairs_or_descs)
+            self._keep = (pairs_or_descs, outs)
+        else:
+            descs, count = pairs_or_descs
+        h = ctypes.c_void_p()
+        _check(L.polymul_batch_create(ctypes.byref(h), descs, count), "polymul_batch_create")
+        self.handle = h
+        self.count = count
+        self.ws_bytes = int(L.polymul_batch_launch_workspace_bytes(h))
+        self.ws = None
+
+    @classmethod
+    def rows(cls, A, B, out, p: int):
+        """Row-wise products of [items, L] matrices into out[items, La + Lb - 1]."""
         items, la = A.shape
         lb = B.shape[1]
-        self.items = items
-        self.descs = (PolymulDesc * items)()
+        descs = (PolymulDesc * items)()
         esz = A.element_size()
         for i in range(items):
-            self.descs[i] = PolymulDesc(p, A.data_ptr() + i * A.stride(0) * esz, la,
-                                        B.data_ptr() + i * B.stride(0) * esz, lb,
-                                        out.data_ptr() + i * out.stride(0) * esz)
-        need = L.polymul_batch_workspace_bytes(self.descs, items)
-        self.ws = _workspace(max(need, 256), A.device)
+            descs[i] = PolymulDesc(p, A.data_ptr() + i * A.stride(0) * esz, la,
+                                   B.data_ptr() + i * B.stride(0) * esz, lb,
+                                   out.data_ptr() + i * out.stride(0) * esz)
+        self = cls((descs, items))
         self._keep = (A, B, out)
+        if self.ws_bytes:
+            self.ws = _workspace(self.ws_bytes, A.device)
+        return self
 
-    def __call__(self, stream=None):
-        _check(load().polymul_modp_batch(self.descs, self.items, _ptr(self.ws), self.ws.numel(), _stream(stream)),
-               "polymul_modp_batch")
+    def __call__(self, stream=None, workspace=None):
+        ws = workspace if workspace is not None else self.ws
+        if self.ws_bytes and ws is None:
+            import torch
+            self.ws = ws = _workspace(self.ws_bytes, torch.device("cuda"))
+        _check(load().polymul_batch_launch(self.handle, _ptr(ws), ws.numel() if ws is not None else 0,
+                                           _stream(stream)), "polymul_batch_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().polymul_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def intmul(a16, b16, out=None, stream=None):
