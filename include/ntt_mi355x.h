@@ -10,8 +10,8 @@
  * section 5.1 places a^_[i]_k at position i.
  *
  * Conventions shared by every entry point:
- *  - Every data pointer is a DEVICE pointer (hipMalloc / torch), 16-byte aligned,
- *    owned by the caller.  The library owns only plan tables.
+ *  - Every data pointer is a DEVICE pointer (hipMalloc / torch) aligned to its
+ *    element size, owned by the caller.  The library owns only plan tables.
  *  - Work is enqueued asynchronously on `hip_stream` (NULL = the default stream).
  *    Argument errors are detected on the host and returned before anything is
  *    enqueued; a failed launch returns NTT_EDEVICE.
@@ -97,9 +97,8 @@ uint64_t ntt_find_prime(uint32_t bits, uint32_t l);
 
 /* Create a plan for length 2^log2n (0 <= log2n <= l where p = k 2^l + 1) modulo p.
  * g = 0 selects the smallest generator; otherwise g must generate F_p^*.
- * The plan precomputes and uploads its twiddle tables (section 5.1: "all the
- * necessary primitive roots and powers are pre-computed and cached") with
- * synchronous copies; `hip_stream` is unused at creation and may be NULL.
+ * The plan precomputes and uploads its twiddle tables (section 5.1 caches every
+ * root and power the transforms need) with synchronous copies; `hip_stream` is unused at creation and may be NULL.
  * A plan is immutable after creation and may be used concurrently on different
  * streams.  Errors: NTT_EINVAL (out == NULL, unknown flags), NTT_EUNSUPPORTED
  * (p < 3 or p >= 2^62, log2n > 26), NTT_ENOTPRIME, NTT_ENOROOT, NTT_ENOMEM. */
