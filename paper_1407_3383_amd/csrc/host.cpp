@@ -710,6 +710,23 @@ int shape_of(uint64_t p, size_t la, size_t lb, ProductShape* s) {
 
 size_t multipass_product_ws(const ProductShape& s) { return s.fused ? 0 : 2 * align256(((size_t)1 << s.L) * (s.wb / 8)); }
 
+int current_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  return device_ctx(dev)->cus;
+}
+
+// Workspace of one fused launch of `count` products of class `cls`.
+size_t fused_launch_ws(int wb, int cls, size_t count, int cus) {
+  const size_t words = fused_park_words(wb, cls);
+  if (!words || !count) return 0;
+  return align256((size_t)fused_grid(wb, cls, count, cus) * words * (wb / 8));
+}
+
+size_t single_product_ws(const ProductShape& s, int cus) {
+  return s.fused ? fused_launch_ws(s.wb, fused_class(s.wb, s.L), 1, cus) : multipass_product_ws(s);
+}
+
 // Two-pass product of one pair (section 5.2 with Algorithm 1): column passes of
 // both operands, the fused row pass, and the inverse column pass into c.
 int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const void* b, size_t lb, void* c, size_t lc,
@@ -769,6 +786,26 @@ FusedItem fused_item(const ntt_plan* pl, const void* a, size_t la, const void* b
   return it;
 }
 
+// Scratch of a batch beyond its descriptor array: the largest park area of its
+// fused launches, or the largest two-pass product (they run one after the other).
+size_t batch_scratch(const std::vector<ProductShape>& shapes, int cus, size_t* nfused_out) {
+  size_t per_class[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  size_t nfused = 0, need = 0;
+  for (const ProductShape& s : shapes) {
+    if (s.L < 0) continue;
+    if (s.fused) {
+      ++nfused;
+      ++per_class[s.wb == 64][fused_class(s.wb, s.L)];
+    } else {
+      need = std::max(need, multipass_product_ws(s));
+    }
+  }
+  for (int w = 0; w < 2; ++w)
+    for (int c = 0; c < 4; ++c) need = std::max(need, fused_launch_ws(w ? 64 : 32, c, per_class[w][c], cus));
+  if (nfused_out) *nfused_out = nfused;
+  return need;
+}
+
 }  // namespace
 
 extern "C" {
@@ -777,7 +814,7 @@ size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
   if (la == 0 || lb == 0) return 0;
   ProductShape s;
   if (shape_of(p, la, lb, &s)) return 0;
-  return multipass_product_ws(s);
+  return single_product_ws(s, current_cus());
 }
 
 int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
@@ -792,7 +829,7 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     const size_t esz = s.wb / 8;
     if (!aligned_to(a, esz) || !aligned_to(b, esz) || !aligned_to(c, esz))
       return fail(NTT_EINVAL, "operands must be %zu-byte aligned", esz);
-    const size_t need = multipass_product_ws(s);
+    const size_t need = single_product_ws(s, current_cus());
     if (ws_bytes < need || (need && !workspace))
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     ntt_plan* pl = nullptr;
@@ -802,6 +839,7 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = nullptr;
+      fb.park = workspace;
       fb.count = 1;
       fb.single = fused_item(pl, a, la, b, lb, c);
       HIP_TRY(launch_fused(s.wb, fused_class(s.wb, s.L), fb, 1, stream));
@@ -816,15 +854,15 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
 
 size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count) {
   if (!d && count) return 0;
-  size_t items = 0, big = 0;
+  std::vector<ProductShape> shapes(count);
   for (size_t i = 0; i < count; ++i) {
+    shapes[i].L = -1;
     if (d[i].la == 0 || d[i].lb == 0) continue;
-    ProductShape s;
-    if (shape_of(d[i].p, d[i].la, d[i].lb, &s)) continue;
-    if (s.fused) ++items;
-    else big = std::max(big, multipass_product_ws(s));
+    if (shape_of(d[i].p, d[i].la, d[i].lb, &shapes[i])) shapes[i].L = -1;
   }
-  return align256(items * sizeof(FusedItem)) + big;
+  size_t nfused = 0;
+  const size_t scratch = batch_scratch(shapes, current_cus(), &nfused);
+  return align256(nfused * sizeof(FusedItem)) + scratch;
 }
 
 int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes, void* hip_stream) {
@@ -833,7 +871,7 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
     if (count == 0) return ok();
     if (!d) return fail(NTT_EINVAL, "descriptor array is NULL");
     std::vector<ProductShape> shapes(count);
-    size_t nfused = 0, big = 0;
+    size_t nfused = 0;
     for (size_t i = 0; i < count; ++i) {
       if (d[i].la == 0 || d[i].lb == 0) {
         shapes[i].L = -1;
@@ -848,10 +886,10 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
       const size_t esz = shapes[i].wb / 8;
       if (!aligned_to(d[i].a, esz) || !aligned_to(d[i].b, esz) || !aligned_to(d[i].c, esz))
         return fail(NTT_EINVAL, "descriptor %zu: operands must be %zu-byte aligned", i, esz);
-      if (shapes[i].fused) ++nfused;
-      else big = std::max(big, multipass_product_ws(shapes[i]));
     }
-    const size_t need = align256(nfused * sizeof(FusedItem)) + big;
+    const int cus = current_cus();
+    const size_t scratch = batch_scratch(shapes, cus, &nfused);
+    const size_t need = align256(nfused * sizeof(FusedItem)) + scratch;
     if (ws_bytes < need || (need && !workspace))
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     int dev = 0;
@@ -881,15 +919,15 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
       int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
       if (rc) return rc;
     }
+    void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
     for (const Group& g : groups) {
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = ditems + g.first;
+      fb.park = bigws;
       fb.count = (int)g.count;
-      const int grid = (int)std::min<size_t>(g.count, 1u << 20);
-      HIP_TRY(launch_fused(g.wb, g.cls, fb, grid, stream));
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, cus), stream));
     }
-    void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
     for (size_t i = 0; i < count; ++i) {
       const ProductShape& s = shapes[i];
       if (s.L < 0 || s.fused) continue;
@@ -915,7 +953,8 @@ struct ntt_batch {
   std::vector<Group> groups;
   struct Big { const ntt_plan* pl; const void *a, *b; void* c; size_t la, lb, lc; };
   std::vector<Big> big;
-  size_t big_ws;
+  size_t big_ws;  // scratch of a launch: park areas and two-pass products
+  int cus;
 };
 
 extern "C" {
@@ -975,8 +1014,9 @@ int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t coun
         return rc;
       }
       bt->big.push_back({pl, d[i].a, d[i].b, d[i].c, d[i].la, d[i].lb, s.lc});
-      bt->big_ws = std::max(bt->big_ws, multipass_product_ws(s));
     }
+    bt->cus = current_cus();
+    bt->big_ws = batch_scratch(shapes, bt->cus, nullptr);
     if (!items.empty()) {
       if (hipMalloc(&bt->ditems, items.size() * sizeof(FusedItem)) != hipSuccess) {
         delete bt;
@@ -1010,8 +1050,9 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = (const FusedItem*)bt->ditems + g.first;
+      fb.park = workspace;
       fb.count = (int)g.count;
-      HIP_TRY(launch_fused(g.wb, g.cls, fb, (int)std::min<size_t>(g.count, 1u << 20), stream));
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), stream));
     }
     for (const auto& b : bt->big) {
       int rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, workspace, stream);
@@ -1068,6 +1109,8 @@ IntLayout int_layout(size_t na, size_t nb) {
     off += align256(na * 4);
     z.o_b32 = off;
     off += align256(nb * 4);
+    z.o_big = off;  // park area of the fused launches
+    off += fused_launch_ws(32, fused_class(32, z.L), 1, current_cus());
   } else {
     z.o_big = off;
     off += 2 * align256(z.N * 4);
@@ -1124,6 +1167,7 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
         FusedBatch fb;
         memset(&fb, 0, sizeof(fb));
         fb.count = 1;
+        fb.park = w + z.o_big;
         fb.single = fused_item(pl, a_in, na, b_in, nb, r[i]);
         HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
       } else {

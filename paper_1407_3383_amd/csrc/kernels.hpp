@@ -10,6 +10,7 @@ namespace nttgpu {
 
 struct FusedBatch {
   const FusedItem* items;  // device array, or NULL to use `single`
+  void* park;              // workspace for parked partial results (fused_park_words per workgroup)
   int count;
   int pad;
   FusedItem single;
@@ -17,6 +18,8 @@ struct FusedBatch {
 
 int fused_class(int word_bits, int log2n);
 int fused_max_log2n(int word_bits);
+size_t fused_park_words(int word_bits, int cls);
+int fused_grid(int word_bits, int cls, size_t count, int cus);
 hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int grid, hipStream_t stream);
 
 // Transform of `batch` vectors that fit one workgroup's LDS (log2n <= lds_max_log2n).

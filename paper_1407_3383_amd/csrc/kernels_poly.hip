@@ -2,22 +2,25 @@
 // entry-wise product, inverse transform and recombination, all inside one
 // workgroup, for transform lengths up to 2^16 (32-bit) / 2^15 (64-bit) residues.
 //
-// A product of transform length N = 2^(d+m) runs as 2^d sub-problems of length
-// 2^m = S that fit in LDS (two operands of S words each).  Sub-problem h starts
+// A product of transform length N = 2^(d+M) runs as 2^d sub-problems of length
+// 2^M = S that fit in LDS (two operands of S words each).  Sub-problem h starts
 // from the fold f_h[j] = sum_k x[j + k S] psi_h^k (the first d forward stages,
 // restricted to block h; psi_h = w_{2^d}^([h]_d)), is transformed, multiplied and
-// inverse-transformed in LDS, and its result is parked in registers.  The last d
-// inverse stages then combine the 2^d partial results register-to-register (each
-// thread holds the same positions j of every partial) and the linear product is
-// written out.  One workgroup serves one product at a time; a launch loops over a
-// descriptor list, so products of any prime and any length in the size class share
-// one launch (section 2.2, Remark 6: several moduli in one vector launch).
+// inverse-transformed in LDS, and its result is parked (in registers, or in a
+// per-workgroup slice of the workspace).  The last d inverse stages then combine
+// the 2^d partial results position by position (each thread handles the same
+// positions j of every partial) and the linear product is written out.  A launch
+// loops over a descriptor list, so products of any prime and any length in the size
+// class share one launch (section 2.2, Remark 6: several moduli in one vector launch).
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace nttgpu {
 
-template <typename T, bool LAZY, int NT, int LOGS, int MAXD>
-__device__ void polymul_item(const FusedItem& it, T* sa, T* sb) {
+// PM = 0: partials in registers; PM = 1: partials in the workspace slice `park`.
+template <typename T, bool LAZY, int NT, int M, int MAXD, int PM>
+__device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* __restrict__ park) {
   const PolyConst<T>* __restrict__ pc = (const PolyConst<T>*)it.cst;
   Arith<T> ar;
   ar.p = pc->p;
@@ -28,87 +31,112 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb) {
   const T* __restrict__ a = (const T*)it.a;
   const T* __restrict__ b = (const T*)it.b;
   T* __restrict__ c = (T*)it.c;
-  const int L = (int)it.log2n;
-  const int m = L < LOGS ? L : LOGS;
-  const int d = L - m;
-  const int S = 1 << m;
+  constexpr int S = 1 << M;
+  constexpr int EPT = (S + NT - 1) / NT;  // positions per thread
+  const int d = (int)it.log2n - M;
   const int nsub = 1 << d;
   const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
-  constexpr int EPT = (1 << LOGS) / NT;
-  T P0[MAXD > 0 ? EPT : 1], P1[MAXD > 1 ? EPT : 1], P2[MAXD > 1 ? EPT : 1];
+  T P0[(PM == 0 && MAXD > 0) ? EPT : 1], P1[(PM == 0 && MAXD > 1) ? EPT : 1], P2[(PM == 0 && MAXD > 1) ? EPT : 1];
+  T* const sv2[2] = {sa, sb};
 
   for (int h = 0; h < nsub; ++h) {
-    // Fold of both operands (zero padding: indices >= la, lb read as 0); the
-    // Montgomery scale 2^bits/N is applied to b here so that the entry-wise
-    // Montgomery product yields a^ b^ / N.
-    for (int j = threadIdx.x; j < S; j += NT) {
-      T fa = 0, fb = 0;
-      for (int k = 0; k < nsub; ++k) {
-        const uint64_t idx = (uint64_t)j + (uint64_t)k * S;
-        if (idx < la) {
-          const T x = a[idx];
-          const T t = k == 0 ? x : ar.red1(ar.shoup(x, pc->fa[h][k].w, pc->fa[h][k].ws));
-          fa = ar.red1(fa + t);
+    // Fold of both operands (indices >= la, lb read as 0); the Montgomery scale
+    // 2^bits/N is applied to b so that the entry-wise Montgomery product yields
+    // a^ b^ / N.
+    const int tf = opaque_tid();
+#pragma unroll 2
+    for (int k0 = 0; k0 < EPT; ++k0) {
+      const int j = tf + k0 * NT;
+      if (j < S) {
+        T fa = 0, fb = 0;
+        for (int k = 0; k < nsub; ++k) {
+          const uint64_t idx = (uint64_t)j + (uint64_t)k * S;
+          if (idx < la) {
+            const T x = a[idx];
+            const T t = k == 0 ? x : ar.red1(ar.shoup(x, pc->fa[h][k].w, pc->fa[h][k].ws));
+            fa = ar.red1(fa + t);
+          }
+          if (idx < lb) {
+            const T t = ar.red1(ar.shoup(b[idx], pc->fb[h][k].w, pc->fb[h][k].ws));
+            fb = ar.red1(fb + t);
+          }
         }
-        if (idx < lb) {
-          const T t = ar.red1(ar.shoup(b[idx], pc->fb[h][k].w, pc->fb[h][k].ws));
-          fb = ar.red1(fb + t);
-        }
+        sa[lidx(j)] = fa;
+        sb[lidx(j)] = fb;
       }
-      sa[lidx(j)] = fa;
-      sb[lidx(j)] = fb;
     }
     __syncthreads();
-    fwd_lds<T, LAZY, NT, true>(ar, sa, sb, m, d, (uint32_t)h, tw);
-    for (int j = threadIdx.x; j < S; j += NT) {
-      T x = sa[lidx(j)], y = sb[lidx(j)];
-      if constexpr (LAZY) {
-        x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
-      } else {
-        x = ar.red1(x);
-        y = ar.red1(y);
+    fwd_lds_ct<T, LAZY, NT, 2, M>(ar, sv2, d, (uint32_t)h, tw);
+    const int tp = opaque_tid();
+#pragma unroll 4
+    for (int k0 = 0; k0 < EPT; ++k0) {
+      const int j = tp + k0 * NT;
+      if (j < S) {
+        T x = sa[lidx(j)], y = sb[lidx(j)];
+        if constexpr (LAZY) {
+          x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
+        } else {
+          x = ar.red1(x);
+          y = ar.red1(y);
+        }
+        T z = ar.mont(x, y);  // (0, 2p)
+        if constexpr (!LAZY) z = ar.red1(z);
+        sa[lidx(j)] = z;
       }
-      T z = ar.mont(x, y);  // (0, 2p)
-      if constexpr (!LAZY) z = ar.red1(z);
-      sa[lidx(j)] = z;
     }
     __syncthreads();
-    inv_lds<T, LAZY, NT>(ar, sa, m, d, (uint32_t)h, twi);
+    inv_lds_ct<T, LAZY, NT, M>(ar, sa, d, (uint32_t)h, twi);
+    const int tr = opaque_tid();
     if (h + 1 < nsub) {
       if constexpr (MAXD > 0) {
 #pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-          const T v = sa[lidx((int)threadIdx.x + k * NT)];
-          if (h == 0) P0[k] = v;
-          else if (h == 1) P1[k] = v;
-          else P2[k] = v;
+        for (int k = 0; k < EPT; ++k) {  // fully unrolled: P0..P2 stay in registers
+          const int j = tr + k * NT;
+          const T v = sa[lidx(j)];
+          if constexpr (PM == 1) {
+            park[(size_t)h * S + j] = v;
+          } else {
+            if (h == 0) P0[k] = v;
+            else if (h == 1) P1[k] = v;
+            else P2[k] = v;
+          }
         }
       }
     } else {
       // Recombination: inverse global stages d-1 .. 0 across the partial results.
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
-        const int j = (int)threadIdx.x + k * NT;
+        const int j = tr + k * NT;
         if (j < S) {
           T v0 = sa[lidx(j)];
+          const uint64_t jj = (uint64_t)j;
           if (d == 0) {
-            if ((uint64_t)j < lc) c[j] = canon_from_inv<LAZY>(ar, v0);
+            if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, v0);
           } else if (d == 1) {
             if constexpr (MAXD > 0) {
-              T x = P0[k];
+              T x = (PM == 1) ? park[j] : P0[k];
               gs_bfly<LAZY>(ar, x, v0, twi[1]);
-              if ((uint64_t)j < lc) c[j] = canon_from_inv<LAZY>(ar, x);
-              if ((uint64_t)j + S < lc) c[j + S] = canon_from_inv<LAZY>(ar, v0);
+              if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, x);
+              if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, v0);
             }
           } else {
             if constexpr (MAXD > 1) {
-              T x0 = P0[k], x1 = P1[k], x2 = P2[k], x3 = v0;
+              T x0, x1, x2;
+              if constexpr (PM == 1) {
+                x0 = park[j];
+                x1 = park[S + j];
+                x2 = park[2 * S + j];
+              } else {
+                x0 = P0[k];
+                x1 = P1[k];
+                x2 = P2[k];
+              }
+              T x3 = v0;
               const TwPair<T> w1 = twi[1], w2 = twi[2], w3 = twi[3];
               gs_bfly<LAZY>(ar, x0, x1, w2);
               gs_bfly<LAZY>(ar, x2, x3, w3);
               gs_bfly<LAZY>(ar, x0, x2, w1);
               gs_bfly<LAZY>(ar, x1, x3, w1);
-              const uint64_t jj = (uint64_t)j;
               if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, x0);
               if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, x1);
               if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, x2);
@@ -122,24 +150,49 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb) {
   }
 }
 
-// Persistent over the item list: workgroup w serves items w, w + G, w + 2G, ...
-template <typename T, int NT, int LOGS, int MAXD>
+template <typename T, int NT, int M, int MAXD, int PM>
+__device__ __forceinline__ void polymul_dispatch_lazy(const FusedItem& it, T* sa, T* sb, T* park) {
+  const PolyConst<T>* pc = (const PolyConst<T>*)it.cst;
+  if (pc->lazy) polymul_item<T, true, NT, M, MAXD, PM>(it, sa, sb, park);
+  else polymul_item<T, false, NT, M, MAXD, PM>(it, sa, sb, park);
+}
+
+// Sub-problem size 2^M for a product of transform length 2^L in a class whose
+// largest sub-problem is 2^LOGS and smallest transform 2^LMIN.
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
+__device__ __forceinline__ void polymul_dispatch(const FusedItem& it, T* sa, T* sb, T* park) {
+  const int L = (int)it.log2n;
+  const int m = L < LOGS ? L : LOGS;
+  if constexpr (LOGS - LMIN >= 10) {
+    if (m <= LOGS - 10) { polymul_dispatch_lazy<T, NT, LOGS - 10, MAXD, PM>(it, sa, sb, park); return; }
+  }
+#define NTT_CASE(K)                                                                    \
+  if constexpr (LOGS - LMIN >= K) {                                                    \
+    if (m == LOGS - K) { polymul_dispatch_lazy<T, NT, LOGS - K, MAXD, PM>(it, sa, sb, park); return; } \
+  }
+  NTT_CASE(9) NTT_CASE(8) NTT_CASE(7) NTT_CASE(6) NTT_CASE(5) NTT_CASE(4) NTT_CASE(3) NTT_CASE(2) NTT_CASE(1)
+#undef NTT_CASE
+  polymul_dispatch_lazy<T, NT, LOGS, MAXD, PM>(it, sa, sb, park);
+}
+
+// Workgroup w serves items w, w + G, w + 2G, ...; with PM = 1 it parks partial
+// results in its own workspace slice of 3 * 2^LOGS words.
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
 __global__ __launch_bounds__(NT) void polymul_fused_kernel(FusedBatch batch) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
   T* sb = sa + lds_words(1 << LOGS);
+  T* park = PM == 1 ? (T*)batch.park + (size_t)blockIdx.x * 3 * ((size_t)1 << LOGS) : nullptr;
   for (int i = blockIdx.x; i < batch.count; i += gridDim.x) {
     const FusedItem it = batch.items ? batch.items[i] : batch.single;
-    const PolyConst<T>* pc = (const PolyConst<T>*)it.cst;
-    if (pc->lazy) polymul_item<T, true, NT, LOGS, MAXD>(it, sa, sb);
-    else polymul_item<T, false, NT, LOGS, MAXD>(it, sa, sb);
+    polymul_dispatch<T, NT, LOGS, LMIN, MAXD, PM>(it, sa, sb, park);
   }
 }
 
-template <typename T, int NT, int LOGS, int MAXD>
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
 static hipError_t launch_fused_cls(const FusedBatch& batch, int grid, hipStream_t stream) {
   const size_t lds = 2 * (size_t)lds_words(1 << LOGS) * sizeof(T);
-  auto k = polymul_fused_kernel<T, NT, LOGS, MAXD>;
+  auto k = polymul_fused_kernel<T, NT, LOGS, LMIN, MAXD, PM>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, stream, batch);
@@ -163,19 +216,32 @@ int fused_class(int word_bits, int log2n) {
 
 int fused_max_log2n(int word_bits) { return word_bits == 32 ? 16 : 15; }
 
+// Words of workspace per workgroup that parks partial results (class 3 only).
+size_t fused_park_words(int word_bits, int cls) {
+  if (cls != 3) return 0;
+  return word_bits == 32 ? 3 * ((size_t)1 << 14) : 0;
+}
+
+// Workgroups of a class-3 launch (its items loop over this many workgroups).
+int fused_grid(int word_bits, int cls, size_t count, int cus) {
+  (void)word_bits;
+  if (cls == 3) return (int)std::min<size_t>(count, (size_t)cus);
+  return (int)std::min<size_t>(count, (size_t)1 << 20);
+}
+
 hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int grid, hipStream_t stream) {
   if (word_bits == 32) {
     switch (cls) {
-      case 0: return launch_fused_cls<uint32_t, 64, 10, 0>(batch, grid, stream);
-      case 1: return launch_fused_cls<uint32_t, 256, 12, 0>(batch, grid, stream);
-      case 2: return launch_fused_cls<uint32_t, 512, 13, 0>(batch, grid, stream);
-      case 3: return launch_fused_cls<uint32_t, 1024, 14, 2>(batch, grid, stream);
+      case 0: return launch_fused_cls<uint32_t, 64, 10, 0, 0, 0>(batch, grid, stream);
+      case 1: return launch_fused_cls<uint32_t, 256, 12, 11, 0, 0>(batch, grid, stream);
+      case 2: return launch_fused_cls<uint32_t, 512, 13, 13, 0, 0>(batch, grid, stream);
+      case 3: return launch_fused_cls<uint32_t, 1024, 14, 14, 2, 1>(batch, grid, stream);
     }
   } else {
     switch (cls) {
-      case 0: return launch_fused_cls<uint64_t, 64, 10, 0>(batch, grid, stream);
-      case 1: return launch_fused_cls<uint64_t, 256, 12, 0>(batch, grid, stream);
-      case 3: return launch_fused_cls<uint64_t, 1024, 13, 2>(batch, grid, stream);
+      case 0: return launch_fused_cls<uint64_t, 64, 10, 0, 0, 0>(batch, grid, stream);
+      case 1: return launch_fused_cls<uint64_t, 256, 12, 11, 0, 0>(batch, grid, stream);
+      case 3: return launch_fused_cls<uint64_t, 512, 13, 13, 2, 0>(batch, grid, stream);
     }
   }
   return hipErrorInvalidValue;

@@ -23,6 +23,15 @@
 namespace nttgpu {
 
 __device__ __forceinline__ int lidx(int e) { return e + (e >> 5); }
+
+// threadIdx.x behind an empty asm barrier: address arithmetic derived from it is
+// recomputed where it is used instead of being hoisted out of the item and
+// sub-problem loops (which would keep dozens of addresses live and spill).
+__device__ __forceinline__ int opaque_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
 __host__ __device__ constexpr int lds_words(int n) { return n + (n >> 5); }
 
 template <typename T, bool LAZY, int R, int NT, bool TWO>
@@ -231,6 +240,127 @@ __device__ void inv_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m,
     case 3: inv_round_multi<T, LAZY, 3, NT>(ar, s, vs, nvec, m, 0, twi); __syncthreads(); break;
     default: break;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time-size variants.  With the vector length 2^M and the round's first
+// stage t0 known at compile time, the padded LDS offset of every cluster element
+// is lidx(base) + off(c), off(c) = (c << ls) + ((c << ls) >> 5): one address per
+// cluster, the rest are instruction immediates.  (Every cluster spans an aligned
+// block of 2^(M-t0) elements whose start is a multiple of 32 or which lies inside
+// one 32-word line, which is what makes the offset independent of the cluster.)
+template <int R, int LS>
+struct ClusterOff {
+  static constexpr int off(int c) { return (c << LS) + ((c << LS) >> 5); }
+};
+
+template <typename T, bool LAZY, int R, int NT, int NV, int M, int T0>
+__device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
+                                             const TwPair<T>* __restrict__ tw) {
+  constexpr int C = 1 << R;
+  constexpr int LS = M - T0 - R;
+  constexpr int NCL = 1 << (M - R);
+#pragma unroll 1
+  for (int q = opaque_tid(); q < NCL; q += NT) {
+    const int b = q >> LS;
+    const int base = (b << (M - T0)) + (q & ((1 << LS) - 1));
+    const int lb = lidx(base);
+    T x[NV][C];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int c = 0; c < C; ++c) x[v][c] = sv[v][lb + ClusterOff<R, LS>::off(c)];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int s = d + T0 + u;
+      const int half = 1 << (R - 1 - u);
+      const TwPair<T>* twu = tw + (1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u));
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) {
+        const TwPair<T> w = twu[vv];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (vv << (R - u)) + c2;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) ct_bfly<LAZY>(ar, x[v][c], x[v][c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int c = 0; c < C; ++c) sv[v][lb + ClusterOff<R, LS>::off(c)] = x[v][c];
+  }
+}
+
+template <typename T, bool LAZY, int R, int NT, int M, int T0>
+__device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, uint32_t h,
+                                             const TwPair<T>* __restrict__ twi) {
+  constexpr int C = 1 << R;
+  constexpr int LS = M - T0 - R;
+  constexpr int NCL = 1 << (M - R);
+#pragma unroll 1
+  for (int q = opaque_tid(); q < NCL; q += NT) {
+    const int b = q >> LS;
+    const int base = (b << (M - T0)) + (q & ((1 << LS) - 1));
+    const int lb = lidx(base);
+    T x[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[c] = sa[lb + ClusterOff<R, LS>::off(c)];
+#pragma unroll
+    for (int u = R - 1; u >= 0; --u) {
+      const int s = d + T0 + u;
+      const int half = 1 << (R - 1 - u);
+      const TwPair<T>* twu = twi + (1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u));
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) {
+        const TwPair<T> w = twu[vv];
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int c = (vv << (R - u)) + c2;
+          gs_bfly<LAZY>(ar, x[c], x[c + half], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa[lb + ClusterOff<R, LS>::off(c)] = x[c];
+  }
+}
+
+// Rounds of the forward transform: first the M mod 4 leftover stages, then radix 16.
+template <typename T, bool LAZY, int NT, int NV, int M, int T0>
+__device__ __forceinline__ void fwd_rounds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
+                                              const TwPair<T>* __restrict__ tw) {
+  if constexpr (T0 < M) {
+    constexpr int R = (T0 == 0 && (M & 3)) ? (M & 3) : 4;
+    fwd_round_ct<T, LAZY, R, NT, NV, M, T0>(ar, sv, d, h, tw);
+    __syncthreads();
+    fwd_rounds_ct<T, LAZY, NT, NV, M, T0 + R>(ar, sv, d, h, tw);
+  }
+}
+
+template <typename T, bool LAZY, int NT, int M, int T0END>
+__device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h,
+                                              const TwPair<T>* __restrict__ twi) {
+  // processes the round that ends at T0END (exclusive), then the earlier ones
+  if constexpr (T0END > 0) {
+    constexpr int R = (T0END == (M & 3)) ? (M & 3) : 4;
+    constexpr int T0 = T0END - R;
+    inv_round_ct<T, LAZY, R, NT, M, T0>(ar, sa, d, h, twi);
+    __syncthreads();
+    inv_rounds_ct<T, LAZY, NT, M, T0>(ar, sa, d, h, twi);
+  }
+}
+
+template <typename T, bool LAZY, int NT, int NV, int M>
+__device__ __forceinline__ void fwd_lds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
+                                           const TwPair<T>* __restrict__ tw) {
+  fwd_rounds_ct<T, LAZY, NT, NV, M, 0>(ar, sv, d, h, tw);
+}
+
+template <typename T, bool LAZY, int NT, int M>
+__device__ __forceinline__ void inv_lds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, const TwPair<T>* __restrict__ twi) {
+  inv_rounds_ct<T, LAZY, NT, M, M>(ar, sa, d, h, twi);
 }
 
 }  // namespace nttgpu
