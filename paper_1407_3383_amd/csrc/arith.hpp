@@ -17,6 +17,29 @@ struct TwPair {
   T ws;  // floor(w * 2^bits(T) / p): the precomputed multiplicand of Function 8
 };
 
+// Global-address-space views of device pointers.  Loads through them are
+// global_load (not flat) instructions: the compiler knows they cannot alias LDS, so
+// it can issue them early and wait for them separately from LDS traffic.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+using gcptr = const __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gcptr<T> gconst(const void* p) {
+  return (gcptr<T>)(const T*)p;
+}
+template <typename T>
+__device__ __forceinline__ gptr<T> gmut(void* p) {
+  return (gptr<T>)(T*)p;
+}
+template <typename T>
+__device__ __forceinline__ TwPair<T> ldtw(gcptr<TwPair<T>> p) {
+  TwPair<T> t;
+  t.w = p->w;
+  t.ws = p->ws;
+  return t;
+}
+
 template <typename T>
 struct Arith;
 

@@ -20,17 +20,18 @@ namespace nttgpu {
 
 // PM = 0: partials in registers; PM = 1: partials in the workspace slice `park`.
 template <typename T, bool LAZY, int NT, int M, int MAXD, int PM>
-__device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* __restrict__ park) {
+__device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic) {
+  const gptr<T> park = gmut<T>(park_generic);
   const PolyConst<T>* __restrict__ pc = (const PolyConst<T>*)it.cst;
   Arith<T> ar;
   ar.p = pc->p;
   ar.p2 = pc->p2;
   ar.pinv = pc->pinv;
-  const TwPair<T>* __restrict__ tw = (const TwPair<T>*)it.tw;
-  const TwPair<T>* __restrict__ twi = (const TwPair<T>*)it.twi;
-  const T* __restrict__ a = (const T*)it.a;
-  const T* __restrict__ b = (const T*)it.b;
-  T* __restrict__ c = (T*)it.c;
+  const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(it.tw);
+  const gcptr<TwPair<T>> twi = gconst<TwPair<T>>(it.twi);
+  const gcptr<T> a = gconst<T>(it.a);
+  const gcptr<T> b = gconst<T>(it.b);
+  const gptr<T> c = gmut<T>(it.c);
   constexpr int S = 1 << M;
   constexpr int EPT = (S + NT - 1) / NT;  // positions per thread
   const int d = (int)it.log2n - M;
@@ -42,27 +43,46 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* __restrict__ 
   for (int h = 0; h < nsub; ++h) {
     // Fold of both operands (indices >= la, lb read as 0); the Montgomery scale
     // 2^bits/N is applied to b so that the entry-wise Montgomery product yields
-    // a^ b^ / N.
-    const int tf = opaque_tid();
-#pragma unroll 2
-    for (int k0 = 0; k0 < EPT; ++k0) {
-      const int j = tf + k0 * NT;
-      if (j < S) {
-        T fa = 0, fb = 0;
-        for (int k = 0; k < nsub; ++k) {
-          const uint64_t idx = (uint64_t)j + (uint64_t)k * S;
-          if (idx < la) {
-            const T x = a[idx];
-            const T t = k == 0 ? x : ar.red1(ar.shoup(x, pc->fa[h][k].w, pc->fa[h][k].ws));
-            fa = ar.red1(fa + t);
-          }
-          if (idx < lb) {
-            const T t = ar.red1(ar.shoup(b[idx], pc->fb[h][k].w, pc->fb[h][k].ws));
-            fb = ar.red1(fb + t);
+    // a^ b^ / N.  The terms k = 0, 1 of every position of the thread are requested
+    // together (one HBM round trip); terms k >= 2 exist only when an operand is
+    // longer than 2S and take a second loop.
+    {
+      const TwPair<T> fa1 = pc->fa[h][1], fb0 = pc->fb[h][0], fb1 = pc->fb[h][1];
+      constexpr int FB = EPT < 8 ? EPT : 8;  // positions whose loads are in flight together
+#pragma unroll 1
+      for (int kb = 0; kb < EPT; kb += FB) {
+        const int tf = opaque_tid() + kb * NT;
+        T xa0[FB], xa1[FB], xb0[FB], xb1[FB];
+#pragma unroll
+        for (int k0 = 0; k0 < FB; ++k0) {
+          const uint64_t j = (uint64_t)(tf + k0 * NT);
+          const bool in = j < (uint64_t)S;
+          xa0[k0] = (in && j < la) ? a[j] : (T)0;
+          xb0[k0] = (in && j < lb) ? b[j] : (T)0;
+          xa1[k0] = (in && nsub > 1 && j + S < la) ? a[j + S] : (T)0;
+          xb1[k0] = (in && nsub > 1 && j + S < lb) ? b[j + S] : (T)0;
+        }
+#pragma unroll
+        for (int k0 = 0; k0 < FB; ++k0) {
+          const int j = tf + k0 * NT;
+          if (j < S) {
+            T fa = xa0[k0];
+            T fb = ar.red1(ar.shoup(xb0[k0], fb0.w, fb0.ws));
+            if (nsub > 1) {
+              fa = ar.red1(fa + ar.red1(ar.shoup(xa1[k0], fa1.w, fa1.ws)));
+              fb = ar.red1(fb + ar.red1(ar.shoup(xb1[k0], fb1.w, fb1.ws)));
+            }
+            if (nsub > 2 && (uint64_t)2 * S < (la > lb ? la : lb)) {
+              for (int k = 2; k < nsub; ++k) {
+                const uint64_t idx = (uint64_t)j + (uint64_t)k * S;
+                if (idx < la) fa = ar.red1(fa + ar.red1(ar.shoup(a[idx], pc->fa[h][k].w, pc->fa[h][k].ws)));
+                if (idx < lb) fb = ar.red1(fb + ar.red1(ar.shoup(b[idx], pc->fb[h][k].w, pc->fb[h][k].ws)));
+              }
+            }
+            sa[lidx(j)] = fa;
+            sb[lidx(j)] = fb;
           }
         }
-        sa[lidx(j)] = fa;
-        sb[lidx(j)] = fb;
       }
     }
     __syncthreads();
@@ -104,6 +124,23 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* __restrict__ 
       }
     } else {
       // Recombination: inverse global stages d-1 .. 0 across the partial results.
+      T q0[EPT], q1[EPT], q2[EPT];
+      if constexpr (PM == 1 && MAXD > 0) {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {  // parked partials, one round trip
+          const int j = tr + k * NT;
+          q0[k] = (d >= 1) ? park[j] : (T)0;
+          q1[k] = (d >= 2) ? park[S + j] : (T)0;
+          q2[k] = (d >= 2) ? park[2 * S + j] : (T)0;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < EPT; ++k) {
+          q0[k] = (MAXD > 0) ? P0[k] : (T)0;
+          q1[k] = (MAXD > 1) ? P1[k] : (T)0;
+          q2[k] = (MAXD > 1) ? P2[k] : (T)0;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int j = tr + k * NT;
@@ -114,25 +151,15 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* __restrict__ 
             if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, v0);
           } else if (d == 1) {
             if constexpr (MAXD > 0) {
-              T x = (PM == 1) ? park[j] : P0[k];
-              gs_bfly<LAZY>(ar, x, v0, twi[1]);
+              T x = q0[k];
+              gs_bfly<LAZY>(ar, x, v0, ldtw<T>(twi + 1));
               if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, x);
               if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, v0);
             }
           } else {
             if constexpr (MAXD > 1) {
-              T x0, x1, x2;
-              if constexpr (PM == 1) {
-                x0 = park[j];
-                x1 = park[S + j];
-                x2 = park[2 * S + j];
-              } else {
-                x0 = P0[k];
-                x1 = P1[k];
-                x2 = P2[k];
-              }
-              T x3 = v0;
-              const TwPair<T> w1 = twi[1], w2 = twi[2], w3 = twi[3];
+              T x0 = q0[k], x1 = q1[k], x2 = q2[k], x3 = v0;
+              const TwPair<T> w1 = ldtw<T>(twi + 1), w2 = ldtw<T>(twi + 2), w3 = ldtw<T>(twi + 3);
               gs_bfly<LAZY>(ar, x0, x1, w2);
               gs_bfly<LAZY>(ar, x2, x3, w3);
               gs_bfly<LAZY>(ar, x0, x2, w1);

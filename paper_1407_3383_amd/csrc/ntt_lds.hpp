@@ -256,7 +256,7 @@ struct ClusterOff {
 
 template <typename T, bool LAZY, int R, int NT, int NV, int M, int T0>
 __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
-                                             const TwPair<T>* __restrict__ tw) {
+                                             gcptr<TwPair<T>> tw) {
   constexpr int C = 1 << R;
   constexpr int LS = M - T0 - R;
   constexpr int NCL = 1 << (M - R);
@@ -265,6 +265,15 @@ __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[
     const int b = q >> LS;
     const int base = (b << (M - T0)) + (q & ((1 << LS) - 1));
     const int lb = lidx(base);
+    // all 2^R - 1 twiddles of the cluster, requested before the LDS reads
+    TwPair<T> w[C - 1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t s = (uint32_t)(d + T0 + u);
+      gcptr<TwPair<T>> twu = tw + ((1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u)));
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) w[(1 << u) - 1 + vv] = ldtw<T>(twu + vv);
+    }
     T x[NV][C];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -272,17 +281,15 @@ __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[
       for (int c = 0; c < C; ++c) x[v][c] = sv[v][lb + ClusterOff<R, LS>::off(c)];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int s = d + T0 + u;
       const int half = 1 << (R - 1 - u);
-      const TwPair<T>* twu = tw + (1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u));
 #pragma unroll
       for (int vv = 0; vv < (1 << u); ++vv) {
-        const TwPair<T> w = twu[vv];
+        const TwPair<T> ww = w[(1 << u) - 1 + vv];
 #pragma unroll
         for (int c2 = 0; c2 < half; ++c2) {
           const int c = (vv << (R - u)) + c2;
 #pragma unroll
-          for (int v = 0; v < NV; ++v) ct_bfly<LAZY>(ar, x[v][c], x[v][c + half], w);
+          for (int v = 0; v < NV; ++v) ct_bfly<LAZY>(ar, x[v][c], x[v][c + half], ww);
         }
       }
     }
@@ -294,8 +301,7 @@ __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[
 }
 
 template <typename T, bool LAZY, int R, int NT, int M, int T0>
-__device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, uint32_t h,
-                                             const TwPair<T>* __restrict__ twi) {
+__device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   constexpr int C = 1 << R;
   constexpr int LS = M - T0 - R;
   constexpr int NCL = 1 << (M - R);
@@ -304,21 +310,27 @@ __device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, u
     const int b = q >> LS;
     const int base = (b << (M - T0)) + (q & ((1 << LS) - 1));
     const int lb = lidx(base);
+    TwPair<T> w[C - 1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t s = (uint32_t)(d + T0 + u);
+      gcptr<TwPair<T>> twu = twi + ((1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u)));
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) w[(1 << u) - 1 + vv] = ldtw<T>(twu + vv);
+    }
     T x[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) x[c] = sa[lb + ClusterOff<R, LS>::off(c)];
 #pragma unroll
     for (int u = R - 1; u >= 0; --u) {
-      const int s = d + T0 + u;
       const int half = 1 << (R - 1 - u);
-      const TwPair<T>* twu = twi + (1u << s) + ((h << (T0 + u)) | ((uint32_t)b << u));
 #pragma unroll
       for (int vv = 0; vv < (1 << u); ++vv) {
-        const TwPair<T> w = twu[vv];
+        const TwPair<T> ww = w[(1 << u) - 1 + vv];
 #pragma unroll
         for (int c2 = 0; c2 < half; ++c2) {
           const int c = (vv << (R - u)) + c2;
-          gs_bfly<LAZY>(ar, x[c], x[c + half], w);
+          gs_bfly<LAZY>(ar, x[c], x[c + half], ww);
         }
       }
     }
@@ -330,7 +342,7 @@ __device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, u
 // Rounds of the forward transform: first the M mod 4 leftover stages, then radix 16.
 template <typename T, bool LAZY, int NT, int NV, int M, int T0>
 __device__ __forceinline__ void fwd_rounds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
-                                              const TwPair<T>* __restrict__ tw) {
+                                              gcptr<TwPair<T>> tw) {
   if constexpr (T0 < M) {
     constexpr int R = (T0 == 0 && (M & 3)) ? (M & 3) : 4;
     fwd_round_ct<T, LAZY, R, NT, NV, M, T0>(ar, sv, d, h, tw);
@@ -340,8 +352,7 @@ __device__ __forceinline__ void fwd_rounds_ct(const Arith<T>& ar, T* const (&sv)
 }
 
 template <typename T, bool LAZY, int NT, int M, int T0END>
-__device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h,
-                                              const TwPair<T>* __restrict__ twi) {
+__device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   // processes the round that ends at T0END (exclusive), then the earlier ones
   if constexpr (T0END > 0) {
     constexpr int R = (T0END == (M & 3)) ? (M & 3) : 4;
@@ -354,12 +365,12 @@ __device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, 
 
 template <typename T, bool LAZY, int NT, int NV, int M>
 __device__ __forceinline__ void fwd_lds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
-                                           const TwPair<T>* __restrict__ tw) {
+                                           gcptr<TwPair<T>> tw) {
   fwd_rounds_ct<T, LAZY, NT, NV, M, 0>(ar, sv, d, h, tw);
 }
 
 template <typename T, bool LAZY, int NT, int M>
-__device__ __forceinline__ void inv_lds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, const TwPair<T>* __restrict__ twi) {
+__device__ __forceinline__ void inv_lds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   inv_rounds_ct<T, LAZY, NT, M, M>(ar, sa, d, h, twi);
 }
 
