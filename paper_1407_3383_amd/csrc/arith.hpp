@@ -32,6 +32,21 @@ template <typename T>
 __device__ __forceinline__ gptr<T> gmut(void* p) {
   return (gptr<T>)(T*)p;
 }
+// Value known to be equal in every lane, moved to scalar registers.
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+  return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+__device__ __forceinline__ const void* uni(const void* x) { return (const void*)uni((uint64_t)(uintptr_t)x); }
+__device__ __forceinline__ void* uni(void* x) { return (void*)uni((uint64_t)(uintptr_t)x); }
+template <typename T>
+__device__ __forceinline__ TwPair<T> uni(const TwPair<T>& t) {
+  TwPair<T> r;
+  r.w = uni(t.w);
+  r.ws = uni(t.ws);
+  return r;
+}
+
 template <typename T>
 __device__ __forceinline__ TwPair<T> ldtw(gcptr<TwPair<T>> p) {
   TwPair<T> t;

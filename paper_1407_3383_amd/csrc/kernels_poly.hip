@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "ntt_wave.hpp"
 
 namespace nttgpu {
 
@@ -86,26 +87,52 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
       }
     }
     __syncthreads();
-    fwd_lds_ct<T, LAZY, NT, 2, M>(ar, sv2, d, (uint32_t)h, tw);
-    const int tp = opaque_tid();
-#pragma unroll 4
-    for (int k0 = 0; k0 < EPT; ++k0) {
-      const int j = tp + k0 * NT;
-      if (j < S) {
-        T x = sa[lidx(j)], y = sb[lidx(j)];
-        if constexpr (LAZY) {
-          x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
-        } else {
-          x = ar.red1(x);
-          y = ar.red1(y);
+    if constexpr (M >= 10) {
+      // Top M-10 stages across the workgroup, the other 10 inside each wave's
+      // 1024-word block; the entry-wise product happens in registers between the
+      // forward and the inverse wave-local rounds.
+      fwd_G<T, LAZY, NT, 2, M>(ar, sv2, d, (uint32_t)h, tw);
+      if ((opaque_tid() >> 6) < (1 << (M - 10))) {
+        T x[2][16];
+        fwd_W<T, LAZY, 2, M>(ar, sv2, d, (uint32_t)h, tw, x);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          T xa = x[0][i], yb = x[1][i];
+          if constexpr (LAZY) {
+            xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
+          } else {
+            xa = ar.red1(xa);
+            yb = ar.red1(yb);
+          }
+          T z = ar.mont(xa, yb);  // (0, 2p)
+          if constexpr (!LAZY) z = ar.red1(z);
+          x[0][i] = z;
         }
-        T z = ar.mont(x, y);  // (0, 2p)
-        if constexpr (!LAZY) z = ar.red1(z);
-        sa[lidx(j)] = z;
+        inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
       }
+      inv_G<T, LAZY, NT, M>(ar, sa, d, (uint32_t)h, twi);
+    } else {
+      fwd_lds_ct<T, LAZY, NT, 2, M>(ar, sv2, d, (uint32_t)h, tw);
+      const int tp = opaque_tid();
+#pragma unroll 4
+      for (int k0 = 0; k0 < EPT; ++k0) {
+        const int j = tp + k0 * NT;
+        if (j < S) {
+          T x = sa[lidx(j)], y = sb[lidx(j)];
+          if constexpr (LAZY) {
+            x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
+          } else {
+            x = ar.red1(x);
+            y = ar.red1(y);
+          }
+          T z = ar.mont(x, y);  // (0, 2p)
+          if constexpr (!LAZY) z = ar.red1(z);
+          sa[lidx(j)] = z;
+        }
+      }
+      __syncthreads();
+      inv_lds_ct<T, LAZY, NT, M>(ar, sa, d, (uint32_t)h, twi);
     }
-    __syncthreads();
-    inv_lds_ct<T, LAZY, NT, M>(ar, sa, d, (uint32_t)h, twi);
     const int tr = opaque_tid();
     if (h + 1 < nsub) {
       if constexpr (MAXD > 0) {
@@ -177,11 +204,211 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
   }
 }
 
+// Wave-local variant (10 <= M <= 14, NT = 2^(M-4) threads doing wave work).
+// Per sub-problem: one "boundary" phase and one wave phase, two barriers.
+//  boundary(h): for each of the thread's clusters {q + 1024 c}:
+//     - request the fold inputs of sub-problem h (the same positions for every h),
+//     - finish sub-problem h-1: its top inverse stages (G'), then park the partial or,
+//       after the last one, recombine with the parked partials and store c,
+//     - fold sub-problem h, run its top forward stages (G) on both operands, store
+//       the clusters to LDS;
+//  wave(h): the wave-local forward rounds of both operands, the entry-wise
+//     product in registers and the wave-local inverse rounds.
+// G'(h-1) and G(h) touch the same elements of the same thread, so no barrier
+// separates them, and the fold loads are in flight while G' computes.
+template <typename T, bool LAZY, int NT, int M, int MAXD>
+__device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa, T* sb, T* park_generic) {
+  static_assert(M >= 10 && M <= 14, "wave-local sub-problems span 2^10 .. 2^14 words");
+  // the descriptor is the same for the whole workgroup: keep it in scalar registers
+  FusedItem it;
+  it.a = uni(it_in.a);
+  it.b = uni(it_in.b);
+  it.c = uni(it_in.c);
+  it.la = uni((uint64_t)it_in.la);
+  it.lb = uni((uint64_t)it_in.lb);
+  it.cst = uni(it_in.cst);
+  it.tw = uni(it_in.tw);
+  it.twi = uni(it_in.twi);
+  it.log2n = uni(it_in.log2n);
+  const gptr<T> park = gmut<T>(uni((void*)park_generic));
+  const gcptr<PolyConst<T>> pc = gconst<PolyConst<T>>(it.cst);
+  Arith<T> ar;
+  ar.p = uni(pc->p);
+  ar.p2 = uni(pc->p2);
+  ar.pinv = uni(pc->pinv);
+  const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(it.tw);
+  const gcptr<TwPair<T>> twi = gconst<TwPair<T>>(it.twi);
+  const gcptr<T> a = gconst<T>(it.a);
+  const gcptr<T> b = gconst<T>(it.b);
+  const gptr<T> c = gmut<T>(it.c);
+  constexpr int S = 1 << M;
+  constexpr int R = M - 10;           // top stages done across the workgroup
+  constexpr int C = 1 << R;           // elements per top-stage cluster
+  constexpr int CPT = 1024 / NT > 0 ? 1024 / NT : 1;  // clusters per thread
+  constexpr int EPT = CPT * C;        // positions per thread
+  const int d = (int)it.log2n - M;
+  const int nsub = 1 << d;
+  const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
+  const bool more_terms = nsub > 2 && (uint64_t)2 * S < (la > lb ? la : lb);
+  T* const sv2[2] = {sa, sb};
+
+  // G' (top inverse stages) of sub-problem hp on the thread's clusters; hands each
+  // finished value to `sink(e, j, value)`.
+  auto finish = [&](int hp, int t0, auto&& sink) {
+    TwPair<T> wi[C > 1 ? C - 1 : 1];
+    if constexpr (R > 0) cluster_twiddles<T, R, true>(wi, twi, d, 0, (uint32_t)hp, 0u);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int q = t0 + i * NT;
+      const int lb0 = lidx(q);
+      T v[C];
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
+      if constexpr (R > 0) cluster_inv<T, LAZY, R>(ar, v, wi);
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) sink(i * C + cc, q + 1024 * cc, v[cc]);
+    }
+  };
+
+  for (int h = 0; h < nsub; ++h) {
+    const int t0 = opaque_tid();
+    // ---- boundary phase: fold inputs in flight, G' of h-1 and park, fold + G of h
+    T x0[EPT], x1[EPT], y0[EPT], y1[EPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const int e = i * C + cc;
+        const uint64_t j = (uint64_t)(t0 + i * NT) + 1024u * cc;
+        x0[e] = j < la ? a[j] : (T)0;
+        y0[e] = j < lb ? b[j] : (T)0;
+        x1[e] = (nsub > 1 && j + S < la) ? a[j + S] : (T)0;
+        y1[e] = (nsub > 1 && j + S < lb) ? b[j + S] : (T)0;
+      }
+    if constexpr (MAXD > 0) {
+      if (h > 0) finish(h - 1, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
+    }
+    {
+      const TwPair<T> fa1 = uni(ldtw<T>(&pc->fa[h][1])), fb0 = uni(ldtw<T>(&pc->fb[h][0])), fb1 = uni(ldtw<T>(&pc->fb[h][1]));
+      TwPair<T> wf[C > 1 ? C - 1 : 1];
+      if constexpr (R > 0) cluster_twiddles<T, R, true>(wf, tw, d, 0, (uint32_t)h, 0u);
+#pragma unroll
+      for (int i = 0; i < CPT; ++i) {
+        const int q = t0 + i * NT;
+        T v[2][C];
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const int e = i * C + cc;
+          T fa = x0[e];
+          T fb = ar.red1(ar.shoup(y0[e], fb0.w, fb0.ws));
+          if (nsub > 1) {
+            fa = ar.red1(fa + ar.red1(ar.shoup(x1[e], fa1.w, fa1.ws)));
+            fb = ar.red1(fb + ar.red1(ar.shoup(y1[e], fb1.w, fb1.ws)));
+          }
+          if (more_terms) {
+            const uint64_t j = (uint64_t)q + 1024u * cc;
+            for (int k = 2; k < nsub; ++k) {
+              const uint64_t idx = j + (uint64_t)k * S;
+              if (idx < la) {
+                const TwPair<T> f = ldtw<T>(&pc->fa[h][k]);
+                fa = ar.red1(fa + ar.red1(ar.shoup(a[idx], f.w, f.ws)));
+              }
+              if (idx < lb) {
+                const TwPair<T> f = ldtw<T>(&pc->fb[h][k]);
+                fb = ar.red1(fb + ar.red1(ar.shoup(b[idx], f.w, f.ws)));
+              }
+            }
+          }
+          v[0][cc] = fa;
+          v[1][cc] = fb;
+        }
+        if constexpr (R > 0) cluster_fwd<T, LAZY, R, 2>(ar, v, 0, wf);
+        const int lb0 = lidx(q);
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          sa[lb0 + cc * 1056] = v[0][cc];
+          sb[lb0 + cc * 1056] = v[1][cc];
+        }
+      }
+    }
+    __syncthreads();
+    // ---- wave phase
+    if ((opaque_tid() >> 6) < (1 << (M - 10))) {
+      T x[2][16];
+      fwd_W<T, LAZY, 2, M>(ar, sv2, d, (uint32_t)h, tw, x);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T xa = x[0][i], yb = x[1][i];
+        if constexpr (LAZY) {
+          xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
+        } else {
+          xa = ar.red1(xa);
+          yb = ar.red1(yb);
+        }
+        T z = ar.mont(xa, yb);  // (0, 2p)
+        if constexpr (!LAZY) z = ar.red1(z);
+        x[0][i] = z;
+      }
+      inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
+    }
+    __syncthreads();
+  }
+  // ---- last boundary: G' of the last sub-problem and the recombination
+  {
+    const int t0 = opaque_tid();
+    T q0[EPT], q1[EPT], q2[EPT];
+    if constexpr (MAXD > 0) {
+#pragma unroll
+      for (int i = 0; i < CPT; ++i)
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const int e = i * C + cc;
+          const int j = t0 + i * NT + 1024 * cc;
+          q0[e] = d >= 1 ? park[j] : (T)0;
+          q1[e] = d >= 2 ? park[S + j] : (T)0;
+          q2[e] = d >= 2 ? park[2 * S + j] : (T)0;
+        }
+    }
+    finish(nsub - 1, t0, [&](int e, int j, T v) {
+      const uint64_t jj = (uint64_t)j;
+      if (d == 0) {
+        if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, v);
+      } else if (d == 1) {
+        if constexpr (MAXD > 0) {
+          T u0 = q0[e], u1 = v;
+          gs_bfly<LAZY>(ar, u0, u1, ldtw<T>(twi + 1));
+          if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
+          if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
+        }
+      } else {
+        if constexpr (MAXD > 1) {
+          T u0 = q0[e], u1 = q1[e], u2 = q2[e], u3 = v;
+          const TwPair<T> w1 = uni(ldtw<T>(twi + 1)), w2 = uni(ldtw<T>(twi + 2)), w3 = uni(ldtw<T>(twi + 3));
+          gs_bfly<LAZY>(ar, u0, u1, w2);
+          gs_bfly<LAZY>(ar, u2, u3, w3);
+          gs_bfly<LAZY>(ar, u0, u2, w1);
+          gs_bfly<LAZY>(ar, u1, u3, w1);
+          if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
+          if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
+          if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u2);
+          if (jj + 3 * (uint64_t)S < lc) c[jj + 3 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u3);
+        }
+      }
+    });
+    __syncthreads();
+  }
+}
+
 template <typename T, int NT, int M, int MAXD, int PM>
 __device__ __forceinline__ void polymul_dispatch_lazy(const FusedItem& it, T* sa, T* sb, T* park) {
   const PolyConst<T>* pc = (const PolyConst<T>*)it.cst;
-  if (pc->lazy) polymul_item<T, true, NT, M, MAXD, PM>(it, sa, sb, park);
-  else polymul_item<T, false, NT, M, MAXD, PM>(it, sa, sb, park);
+  if constexpr (M >= 10 && PM == 1) {
+    if (uni(gconst<PolyConst<T>>(uni(it.cst))->lazy)) polymul_item_wave<T, true, NT, M, MAXD>(it, sa, sb, park);
+    else polymul_item_wave<T, false, NT, M, MAXD>(it, sa, sb, park);
+  } else {
+    if (pc->lazy) polymul_item<T, true, NT, M, MAXD, PM>(it, sa, sb, park);
+    else polymul_item<T, false, NT, M, MAXD, PM>(it, sa, sb, park);
+  }
 }
 
 // Sub-problem size 2^M for a product of transform length 2^L in a class whose

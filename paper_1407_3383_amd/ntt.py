@@ -71,6 +71,9 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libntt_mi355x.so is not built (run __graft_entry__.build())")
+    # torch first: its bundled HIP runtime (same soname) must be the one the library
+    # binds to, so that torch's streams and allocations are valid handles for it.
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     u64, sz, vp, u32, ci = ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
     sig = {
