@@ -54,6 +54,10 @@ def main() -> int:
     ap.add_argument("--no-percall", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workload", default="batch",
+                    choices=["batch", "polymul8k", "ntt2_24", "intmul", "serve", "all"],
+                    help="batch (default, the headline line) or one of the other configurations")
+    ap.add_argument("--serve-requests", type=int, default=600)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -74,6 +78,12 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         log("copied %d MiB three times" % args.copy_calibration_mib)
+        return 0
+    if args.workload != "batch":
+        import bench_workloads
+        names = ["polymul8k", "ntt2_24", "intmul", "serve"] if args.workload == "all" else [args.workload]
+        for name in names:
+            print(json.dumps(bench_workloads.run(name, args)), flush=True)
         return 0
     items, L = args.items, 1 << args.log2len
     lc = 2 * L - 1

@@ -1,0 +1,159 @@
+"""Secondary benchmark workloads (bench.py --workload ...): one product of two
+length-4096 operands mod 998244353, a length-2^24 forward + inverse transform mod
+469762049, and the 2^21 x 2^21-limb three-prime integer product.  Each prints one
+JSON line with the same keys as the headline line; inputs are resident in HBM and
+plan creation is outside the timed region."""
+from __future__ import annotations
+
+import sys
+import time
+
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+OPS_PER_BFLY = 9
+HBM_PEAK_GBPS = 8000.0
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _time(fn, stream, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    return wall_ms, e0.elapsed_time(e1) / steps
+
+
+def _line(metric, value, unit, ms, steps, warmup, config, extra):
+    out = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic", "config": config}
+    out.update(extra)
+    return out
+
+
+def run(name, args):
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt
+    stream = torch.cuda.Stream()
+    if name == "polymul8k":
+        p, a, b = inputs.polymul_8k_inputs()
+        da, db = ntt.to_device(a), ntt.to_device(b)
+        dc = torch.empty(8191, dtype=torch.int32, device="cuda")
+        bt = ntt.Batch([(da, db)], [p], [dc])
+        steps = max(args.steps, 200)
+        ms, kms = _time(lambda: bt(stream), stream, steps, 20)
+        bfly = 3 * 4096 * 13
+        _log("polymul8k: %.2f us/product (events %.2f us)" % (ms * 1e3, kms * 1e3))
+        return _line("single polymul mod p latency (Gbutterflies/s)", bfly / (ms * 1e-3) / 1e9, "Gbfly/s", ms, steps, 20,
+                     {"workload": "one product mod 998244353 of two length-4096 operands, transform length 8192"},
+                     {"us_per_product": round(ms * 1e3, 2), "kernel_us": round(kms * 1e3, 2),
+                      "note": "one workgroup on one CU: latency-bound"})
+    if name == "ntt2_24":
+        p, x = inputs.ntt_2_24_inputs()
+        plan = ntt.Plan(p, 24, 3, ntt.NTT_BITREV_OUT | ntt.NTT_BITREV_IN)
+        dx = ntt.to_device(x)
+        n = 1 << 24
+
+        def step():
+            plan.forward(dx, out=dx, stream=stream)
+            plan.inverse(dx, out=dx, stream=stream)
+        steps = max(args.steps, 20)
+        ms, kms = _time(step, stream, steps, 3)
+        torch.cuda.synchronize()
+        ok = bool(torch.equal(dx.cpu(), torch.from_numpy(x.view("int32"))))
+        bfly = 2 * (n // 2) * 24
+        alg = 4 * n * 4  # read + write of both transforms
+        _log("ntt2_24: %.3f ms per forward+inverse (roundtrip identity %s)" % (ms, ok))
+        return _line("forward+inverse NTT 2^24 (Gbutterflies/s)", bfly / (ms * 1e-3) / 1e9, "Gbfly/s", ms, steps, 3,
+                     {"workload": "forward + inverse transform of length 2^24 mod 469762049, TFT order in between"},
+                     {"roundtrip_identity": ok,
+                      "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
+                              "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                              "pass_bytes_per_step": 8 * n * 4},
+                      "alu": {"achieved_Tops": round(bfly * OPS_PER_BFLY / (ms * 1e-3) / 1e12, 3),
+                              "peak_Tops": round(ALU_PEAK_TOPS, 3)}})
+    if name == "intmul":
+        a, b = inputs.intmul_inputs()
+        da, db = ntt.to_device(a), ntt.to_device(b)
+        dc = torch.empty(1 << 21, dtype=torch.int32, device="cuda")
+        L = ntt.load()
+        ws = torch.empty(L.intmul_workspace_bytes(a.size, b.size), dtype=torch.uint8, device="cuda")
+
+        def step():
+            ntt._check(L.intmul_crt(ntt._ptr(da), a.size, ntt._ptr(db), b.size, ntt._ptr(dc), ntt._ptr(ws), ws.numel(),
+                                    ntt._stream(stream)), "intmul_crt")
+        steps = max(args.steps, 10)
+        ms, kms = _time(step, stream, steps, 2)
+        N = 1 << 22
+        bfly = 3 * 3 * (N // 2) * 22
+        alg = 2 * (1 << 21) * 2 + (1 << 21) * 4
+        _log("intmul: %.3f ms per product" % ms)
+        return _line("three-prime integer product 2^25 x 2^25 bits (Gbutterflies/s)", bfly / (ms * 1e-3) / 1e9, "Gbfly/s",
+                     ms, steps, 2,
+                     {"workload": "product of two 2^21-limb (16-bit) integers, primes 998244353, 469762049, 167772161, transform length 2^22"},
+                     {"ms_per_product": round(ms, 4),
+                      "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 2)},
+                      "alu": {"achieved_Tops": round(bfly * OPS_PER_BFLY / (ms * 1e-3) / 1e12, 3),
+                              "peak_Tops": round(ALU_PEAK_TOPS, 3)}})
+    if name == "serve":
+        return run_serve(args)
+    raise ValueError(name)
+
+
+def run_serve(args):
+    """Serving mix: capacity with everything queued at t = 0, then Poisson arrivals
+    at 0.5, 0.8 and 0.95 of that capacity; p50/p99 latency and throughput."""
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt, serve
+    p62 = ntt.find_prime(62, 32)
+    primes = (998244353, 2013265921, p62)
+    n = args.serve_requests
+    specs = inputs.serve_requests(n, primes, 8.0, 20.0, 0)
+    _log("serve: generating %d requests" % n)
+    ops = [inputs.serve_operands(p, L, rid) for (p, L, rid) in specs]
+    total_bfly = sum(serve.butterflies(L, L) for (_, L, _) in specs)
+
+    def make(arrivals):
+        return [serve.Request(rid, p, a, b, arrival=float(t))
+                for (p, L, rid), (a, b), t in zip(specs, ops, arrivals)]
+
+    budget = 8 << 30
+    # warm the plan cache and the kernels
+    warm = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    warm.run(make([0.0] * n), realtime=False)
+    sat = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    wall = sat.run(make([0.0] * n), realtime=False)
+    capacity = n / wall
+    out = {"metric": "serving mix: p50/p99 latency and throughput", "value": round(capacity, 2), "unit": "requests/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
+           "config": {"workload": "%d polymul requests, L = floor(2^U(8,20)), p uniform over {998244353, 2013265921, %d}" % (n, p62),
+                      "hbm_budget_bytes": budget, "streams": 4},
+           "saturated": {"requests_per_s": round(capacity, 2), "Gbfly_per_s": round(total_bfly / wall / 1e9, 2),
+                         **serve.latency_stats(sat.completed)}}
+    levels = {}
+    for frac in (0.5, 0.8, 0.95):
+        arr = inputs.poisson_arrivals(n, frac * capacity, int(frac * 100))
+        srv = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+        w = srv.run(make(arr), realtime=True)
+        st = serve.latency_stats(srv.completed)
+        levels[str(frac)] = {"offered_rps": round(frac * capacity, 2), "achieved_rps": round(n / w, 2),
+                             "Gbfly_per_s": round(total_bfly / w / 1e9, 2), "max_inflight_batches": srv.max_inflight_batches,
+                             "overlapped_admissions": srv.overlapped_admissions, **st}
+        _log("serve at %.2f x capacity: p50 %.3f ms, p99 %.3f ms" % (frac, st["p50_ms"], st["p99_ms"]))
+    out["poisson"] = levels
+    torch.cuda.synchronize()
+    return out

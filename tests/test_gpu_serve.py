@@ -1,0 +1,78 @@
+"""Serving loop (continuous batching by HBM budget): every result is the same when
+the request is served alone and in the mix, bit-exact, and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import numtheory as nt
+from paper_1407_3383_amd import inputs, ntt, serve
+
+from gpu_util import assert_equal_u, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+P62 = nt.largest_prime_below(62, 32)
+PRIMES = (998244353, 2013265921, P62)
+
+
+def _requests(n, rate, lo=8.0, hi=14.0, seed=0):
+    specs = inputs.serve_requests(n, PRIMES, lo, hi, seed)
+    arrivals = inputs.poisson_arrivals(n, rate, seed)
+    out = []
+    for (p, L, rid), t in zip(specs, arrivals):
+        a, b = inputs.serve_operands(p, L, rid)
+        out.append(serve.Request(rid, p, a, b, arrival=float(t)))
+    return out
+
+
+def _alone(r):
+    c = ntt.polymul(ntt.to_device(r.a), ntt.to_device(r.b), r.p)
+    return ntt.to_numpy(c)
+
+
+def test_serve_mix_equals_alone_and_oracle():
+    torch_cuda()
+    reqs = _requests(60, rate=20000.0)
+    say("serve mix of %d requests" % len(reqs))
+    srv = serve.Server(budget_bytes=256 << 20, streams=4, max_batch=16)
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    assert srv.max_inflight_batches >= 2, "no batches overlapped on the device"
+    for r in reqs:
+        assert_equal_u(r.result, _alone(r), "request %d (p=%d, L=%d) mix vs alone" % (r.rid, r.p, r.a.size))
+    for r in reqs[:12]:
+        assert_equal_u(r.result, oracle.polymul_ntt(r.a, r.b, r.p), "request %d vs oracle" % r.rid)
+    stats = serve.latency_stats(srv.completed)
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_serve_small_budget_queues_and_completes():
+    torch_cuda()
+    reqs = _requests(24, rate=1e6, lo=10.0, hi=13.0, seed=1)
+    biggest = max(serve.footprint(r.p, r.a.size, r.b.size) for r in reqs)
+    srv = serve.Server(budget_bytes=biggest + (64 << 10), streams=2, max_batch=8)
+    say("serve with a budget of %d bytes" % srv.arena.budget)
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    for r in reqs:
+        assert_equal_u(r.result, _alone(r), "request %d under a small budget" % r.rid)
+    assert srv.arena.used == 0
+
+
+def test_serve_admits_while_batches_in_flight():
+    torch_cuda()
+    reqs = _requests(80, rate=50000.0, lo=12.0, hi=16.0, seed=2)
+    srv = serve.Server(budget_bytes=512 << 20, streams=4, max_batch=8)
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    assert srv.overlapped_admissions > 0
+    for r in reqs[::7]:
+        assert_equal_u(r.result, _alone(r), "request %d" % r.rid)
+
+
+def test_serve_rejects_request_beyond_budget():
+    torch_cuda()
+    reqs = _requests(2, rate=1000.0, lo=14.0, hi=14.5, seed=3)
+    srv = serve.Server(budget_bytes=4096)
+    with pytest.raises(ValueError):
+        srv.run(reqs)
