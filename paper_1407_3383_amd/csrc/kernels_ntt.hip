@@ -339,7 +339,7 @@ static hipError_t launch_col_t(const PassArgs& a, int L1, int L2, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+hipError_t launch_col_fwd_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
   if (word_bits == 32) {
     if (a.in_u16) return launch_col_t<uint32_t, 1024, kColTileLog32, false, uint16_t>(a, L1, L2, stream);
     return launch_col_t<uint32_t, 1024, kColTileLog32, false, uint32_t>(a, L1, L2, stream);
@@ -347,7 +347,7 @@ hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipS
   return launch_col_t<uint64_t, 512, kColTileLog64, false, uint64_t>(a, L1, L2, stream);
 }
 
-hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+hipError_t launch_col_inv_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
   if (word_bits == 32) return launch_col_t<uint32_t, 1024, kColTileLog32, true, uint32_t>(a, L1, L2, stream);
   return launch_col_t<uint64_t, 512, kColTileLog64, true, uint64_t>(a, L1, L2, stream);
 }
@@ -364,7 +364,7 @@ static hipError_t launch_row_t(const PassArgs& a, int L1, int L2, hipStream_t st
 }
 
 template <int KIND>
-static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+static hipError_t launch_row_kind_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
   if (word_bits == 32) {
     if (L2 <= 10) return launch_row_t<uint32_t, 64, KIND>(a, L1, L2, stream);
     if (L2 <= 12) return launch_row_t<uint32_t, 256, KIND>(a, L1, L2, stream);
@@ -375,15 +375,10 @@ static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int 
   return launch_row_t<uint64_t, 512, KIND>(a, L1, L2, stream);
 }
 
-hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  return launch_row_kind<0>(word_bits, a, L1, L2, stream);
-}
-hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool scale_ninv, hipStream_t stream) {
-  (void)scale_ninv;  // the caller passes the table with n^-1 folded in when asked
-  return launch_row_kind<1>(word_bits, a, L1, L2, stream);
-}
-hipError_t launch_row_polymul(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  return launch_row_kind<2>(word_bits, a, L1, L2, stream);
+hipError_t launch_row_rounds(int word_bits, int kind, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  if (kind == 0) return launch_row_kind_rounds<0>(word_bits, a, L1, L2, stream);
+  if (kind == 1) return launch_row_kind_rounds<1>(word_bits, a, L1, L2, stream);
+  return launch_row_kind_rounds<2>(word_bits, a, L1, L2, stream);
 }
 
 // ----------------------------------------------------------------------------- permutation

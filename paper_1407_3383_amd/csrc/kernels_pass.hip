@@ -1,0 +1,388 @@
+// Two-pass transforms (section 5.1, Algorithm 1) on the wave-local machinery.
+//
+// The vector (length 2^L) is read as 2^L1 rows of 2^L2 contiguous words.
+//  * Column pass: the global stages 0 .. L1-1 are independent length-2^L1
+//    transforms of the 2^L2 strided columns.  A workgroup loads a tile of C adjacent
+//    columns into LDS with coalesced runs of C words, every wave transforms whole
+//    columns with wave-local rounds (no workgroup barrier), and the tile is stored
+//    back.  Columns longer than 2^10 use workgroup rounds.
+//  * Row pass: row r is twisted by G^j, G = w_N^([r]_L1) (step 2; G^j is the product
+//    of two table entries) and transformed (step 3) with the split of ntt_wave.hpp:
+//    the top L2-10 stages on clusters loaded straight from HBM, the other 10 inside
+//    each wave, the result written from registers in the TFT order of step 4.  The
+//    inverse mirrors it; the fused product row pass runs both operands, the
+//    entry-wise product and the inverse in one workgroup.
+#include "kernels.hpp"
+#include "ntt_wave.hpp"
+
+namespace nttgpu {
+
+__device__ __forceinline__ uint32_t brev_u(uint32_t i, int L) { return L == 0 ? 0u : (__brev(i) >> (32 - L)); }
+
+template <typename T>
+__device__ __forceinline__ Arith<T> arith_uni(const void* pcv) {
+  gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(pcv));
+  Arith<T> ar;
+  ar.p = uni(pc->p);
+  ar.p2 = uni(pc->p2);
+  ar.pinv = uni(pc->pinv);
+  return ar;
+}
+
+// x * G^j with G^j = w_N^e read as lo[e mod 2^B] * hi[e >> B]; any word x -> [0, 2p).
+template <typename T>
+__device__ __forceinline__ T twist2(const Arith<T>& ar, T x, uint32_t e, int B, gcptr<TwPair<T>> lo,
+                                    gcptr<TwPair<T>> hi) {
+  const TwPair<T> h = ldtw<T>(hi + (e >> B));
+  const TwPair<T> l = ldtw<T>(lo + (e & ((1u << B) - 1)));
+  return ar.shoup(ar.shoup(x, h.w, h.ws), l.w, l.ws);
+}
+
+// ------------------------------------------------------------------ wave-local columns
+// Stages [T0, T0+R) of V vectors of 2^K words (K <= 10) at LDS stride vs, processed by
+// one wave: work items (vector, cluster) are spread over the 64 lanes.
+template <typename T, bool LAZY, bool INV, int R, int K, int T0, int V>
+__device__ __forceinline__ void vec_round(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> tw) {
+  constexpr int C = 1 << R;
+  constexpr int LS = K - T0 - R;
+  constexpr int NCL = 1 << (K - R);
+  constexpr int ITEMS = V * NCL;
+#pragma unroll 1
+  for (int qq = lane; qq < ITEMS; qq += 64) {
+    const int v = qq / NCL, q = qq % NCL;
+    const int b = q >> LS;
+    const int base = (b << (K - T0)) + (q & ((1 << LS) - 1));
+    T* sv = s + v * vs;
+    const int lb = lidx(base);
+    TwPair<T> w[C - 1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      gcptr<TwPair<T>> p = tw + ((1u << (T0 + u)) + ((uint32_t)b << u));
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) w[(1 << u) - 1 + vv] = ldtw<T>(p + vv);
+    }
+    T x[1][C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[0][c] = sv[lb + ClusterOff<R, LS>::off(c)];
+    if constexpr (INV) cluster_inv<T, LAZY, R>(ar, x[0], w);
+    else cluster_fwd<T, LAZY, R, 1>(ar, x, 0, w);
+#pragma unroll
+    for (int c = 0; c < C; ++c) sv[lb + ClusterOff<R, LS>::off(c)] = x[0][c];
+  }
+}
+
+template <typename T, bool LAZY, int K, int V, int T0>
+__device__ __forceinline__ void vec_fwd_rounds(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> tw) {
+  if constexpr (T0 < K) {
+    constexpr int R = (T0 == 0 && (K & 3)) ? (K & 3) : 4;
+    vec_round<T, LAZY, false, R, K, T0, V>(ar, s, vs, lane, tw);
+    wave_sync();
+    vec_fwd_rounds<T, LAZY, K, V, T0 + R>(ar, s, vs, lane, tw);
+  }
+}
+
+template <typename T, bool LAZY, int K, int V, int T0END>
+__device__ __forceinline__ void vec_inv_rounds(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> twi) {
+  if constexpr (T0END > 0) {
+    constexpr int R = (T0END == (K & 3)) ? (K & 3) : 4;
+    constexpr int T0 = T0END - R;
+    vec_round<T, LAZY, true, R, K, T0, V>(ar, s, vs, lane, twi);
+    wave_sync();
+    vec_inv_rounds<T, LAZY, K, V, T0>(ar, s, vs, lane, twi);
+  }
+}
+
+// Column pass for columns of 2^K words, K <= 10: tiles of C = 2^(TILELOG-K) columns.
+template <typename T, bool LAZY, int NT, int TILELOG, int K, bool INV, typename IN_T>
+__device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, const Arith<T>& ar) {
+  constexpr int LC0 = TILELOG - K;
+  const int LC = LC0 < L2 ? LC0 : L2;
+  const int C = 1 << LC;
+  constexpr int VS = lds_words(1 << K) + 1;
+  const uint64_t tiles_per_vec = 1ull << (L2 - LC);
+  const uint64_t vec = tile / tiles_per_vec;
+  const uint32_t col0 = (uint32_t)(tile % tiles_per_vec) << LC;
+  const int cnt = C << K;
+  const int tid = opaque_tid();
+  const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
+  if constexpr (!INV) {
+    const gcptr<IN_T> in = gconst<IN_T>(uni(A.in)) + vec * A.in_stride;
+    const TwPair<T> sig = uni(ldtw<T>(&pc->sigma));
+    const bool scale = A.scale != 0;
+#pragma unroll 4
+    for (int idx = tid; idx < cnt; idx += NT) {
+      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+      const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+      T x = gi < A.valid ? (T)in[gi] : (T)0;
+      if (scale) x = ar.red1(ar.shoup(x, sig.w, sig.ws));
+      s[cc * VS + lidx(r)] = x;
+    }
+  } else {
+    const gcptr<T> in = gconst<T>(uni(A.in)) + vec * A.in_stride;
+#pragma unroll 4
+    for (int idx = tid; idx < cnt; idx += NT) {
+      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+      s[cc * VS + lidx(r)] = in[((uint64_t)r << L2) + col0 + cc];
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int V = (1 << K) >= 1024 ? 1 : (1024 >> K);  // vectors per wave step: 64 lanes busy
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    constexpr int NW = NT / 64;
+    for (int v0 = wave * V; v0 < C; v0 += NW * V) {
+      if constexpr (INV) vec_inv_rounds<T, LAZY, K, V, K>(ar, s + v0 * VS, VS, lane, gconst<TwPair<T>>(uni(A.twi)));
+      else vec_fwd_rounds<T, LAZY, K, V, 0>(ar, s + v0 * VS, VS, lane, gconst<TwPair<T>>(uni(A.tw)));
+    }
+  }
+  __syncthreads();
+  const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride;
+#pragma unroll 4
+  for (int idx = tid; idx < cnt; idx += NT) {
+    const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+    const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+    const T x = s[cc * VS + lidx(r)];
+    if constexpr (INV) {
+      if (gi < A.valid) out[gi] = canon_from_inv<LAZY>(ar, x);
+    } else {
+      out[gi] = x;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NT, int TILELOG, int K, bool INV, typename IN_T>
+__global__ __launch_bounds__(NT) void col_wave_kernel(PassArgs A, uint64_t ntiles, int L2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* s = (T*)smem_raw;
+  const Arith<T> ar = arith_uni<T>(A.pc);
+  const bool lazy = uni(gconst<PassConst<T>>(uni(A.pc))->lazy) != 0;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    if (lazy) col_wave_body<T, true, NT, TILELOG, K, INV, IN_T>(A, s, t, L2, ar);
+    else col_wave_body<T, false, NT, TILELOG, K, INV, IN_T>(A, s, t, L2, ar);
+  }
+}
+
+// ------------------------------------------------------------------ rows
+// KIND 0: forward (twist, transform); 1: inverse (transform, inverse twist);
+// 2: fused product of two operands (twist both, forward, entry-wise product,
+// inverse, inverse twist).  Rows of 2^M words, 10 <= M <= 14.
+template <typename T, bool LAZY, int NT, int M, int KIND>
+__device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, const Arith<T>& ar) {
+  constexpr int R = M - 10;
+  constexpr int C = 1 << R;
+  constexpr int CPT = 1024 / NT > 0 ? 1024 / NT : 1;
+  const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
+  const int L1 = (int)uni(pc->L1);
+  const int B = (int)uni(pc->B);
+  const uint64_t vec = rowid >> L1;
+  const uint32_t r = (uint32_t)(rowid & ((1u << L1) - 1));
+  const uint32_t Rr = brev_u(r, L1);
+  const uint64_t off = (uint64_t)r << M;
+  const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(uni(A.tw));
+  const gcptr<TwPair<T>> twi = gconst<TwPair<T>>(uni(A.twi));
+  const int t0 = opaque_tid();
+  const int lane = t0 & 63;
+  const uint32_t Bw = (uint32_t)__builtin_amdgcn_readfirstlane(t0 >> 6);
+  const bool wave_active = Bw < (1u << (M - 10));
+  const int wbase = (int)Bw << 10;
+
+  if constexpr (KIND == 0 || KIND == 2) {
+    const gcptr<TwPair<T>> lo = gconst<TwPair<T>>(uni(A.tlo));
+    const gcptr<TwPair<T>> hi = gconst<TwPair<T>>(uni(A.thi));
+    const gcptr<T> ina = gconst<T>(uni(A.in)) + vec * A.in_stride + off;
+    const gcptr<T> inb = gconst<T>(uni(A.in2)) + vec * A.in_stride + off;
+    TwPair<T> wf[C > 1 ? C - 1 : 1];
+    if constexpr (R > 0) cluster_twiddles<T, R, true>(wf, tw, 0, 0, 0u, 0u);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int q = t0 + i * NT;
+      constexpr int NV = KIND == 2 ? 2 : 1;
+      T v[NV][C];
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const uint32_t j = (uint32_t)(q + 1024 * cc);
+        v[0][cc] = ina[j];
+        if constexpr (KIND == 2) v[1][cc] = inb[j];
+      }
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const uint32_t e = (uint32_t)(q + 1024 * cc) * Rr;
+        v[0][cc] = twist2(ar, v[0][cc], e, B, lo, hi);
+        if constexpr (KIND == 2) v[1][cc] = twist2(ar, v[1][cc], e, B, lo, hi);
+      }
+      if constexpr (R > 0) cluster_fwd<T, LAZY, R, NV>(ar, v, 0, wf);
+      const int lb0 = lidx(q);
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        sa[lb0 + cc * 1056] = v[0][cc];
+        if constexpr (KIND == 2) sb[lb0 + cc * 1056] = v[1][cc];
+      }
+    }
+    __syncthreads();
+    if constexpr (KIND == 0) {
+      if (wave_active) {
+        T x[1][16];
+        T* const sv[1] = {sa};
+        fwd_W<T, LAZY, 1, M>(ar, sv, 0, 0u, tw, x);
+        const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride + off;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) out[wbase + 4 * (lane + 64 * k) + c] = canon_from_fwd<LAZY>(ar, x[0][4 * k + c]);
+      }
+      __syncthreads();
+      return;
+    } else {
+      if (wave_active) {
+        T x[2][16];
+        T* const sv[2] = {sa, sb};
+        fwd_W<T, LAZY, 2, M>(ar, sv, 0, 0u, tw, x);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          T xa = x[0][i], yb = x[1][i];
+          if constexpr (LAZY) {
+            xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
+          } else {
+            xa = ar.red1(xa);
+            yb = ar.red1(yb);
+          }
+          T z = ar.mont(xa, yb);  // (0, 2p); the Montgomery scale was applied to b
+          if constexpr (!LAZY) z = ar.red1(z);
+          x[0][i] = z;
+        }
+        inv_W<T, LAZY, M>(ar, sa, 0, 0u, twi, x[0]);
+      }
+      __syncthreads();
+    }
+  } else {
+    // KIND 1: canonical input in the TFT order
+    if (wave_active) {
+      const gcptr<T> in = gconst<T>(uni(A.in)) + vec * A.in_stride + off;
+      T x[16];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[4 * k + c] = in[wbase + 4 * (lane + 64 * k) + c];
+      inv_W<T, LAZY, M>(ar, sa, 0, 0u, twi, x);
+    }
+    __syncthreads();
+  }
+  // top inverse stages, inverse twist, store
+  {
+    const gcptr<TwPair<T>> ilo = gconst<TwPair<T>>(uni(A.tilo));
+    const gcptr<TwPair<T>> ihi = gconst<TwPair<T>>(uni(A.tihi));
+    const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride + off;
+    TwPair<T> wi[C > 1 ? C - 1 : 1];
+    if constexpr (R > 0) cluster_twiddles<T, R, true>(wi, twi, 0, 0, 0u, 0u);
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+      const int q = t0 + i * NT;
+      const int lb0 = lidx(q);
+      T v[C];
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
+      if constexpr (R > 0) cluster_inv<T, LAZY, R>(ar, v, wi);
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const uint32_t j = (uint32_t)(q + 1024 * cc);
+        T y = twist2(ar, v[cc], j * Rr, B, ilo, ihi);
+        if constexpr (!LAZY) y = ar.red1(y);
+        out[j] = y;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NT, int M, int KIND>
+__global__ __launch_bounds__(NT) void row_wave_kernel(PassArgs A, uint64_t nrows) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sa = (T*)smem_raw;
+  T* sb = sa + lds_words(1 << M);
+  const Arith<T> ar = arith_uni<T>(A.pc);
+  const bool lazy = uni(gconst<PassConst<T>>(uni(A.pc))->lazy) != 0;
+  for (uint64_t t = blockIdx.x; t < nrows; t += gridDim.x) {
+    if (lazy) row_wave_body<T, true, NT, M, KIND>(A, sa, sb, t, ar);
+    else row_wave_body<T, false, NT, M, KIND>(A, sa, sb, t, ar);
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static int grid_of(uint64_t items) { return (int)(items < 1048576ull ? items : 1048576ull); }
+
+template <typename T, int NT, int TILELOG, int K, bool INV, typename IN_T>
+static hipError_t launch_col_wave_k(const PassArgs& a, int L2, hipStream_t stream) {
+  constexpr int LC0 = TILELOG - K;
+  const int LC = LC0 < L2 ? LC0 : L2;
+  const uint64_t ntiles = (uint64_t)a.batch << (L2 - LC);
+  const size_t lds = (size_t)(1 << LC) * (lds_words(1 << K) + 1) * sizeof(T);
+  auto k = col_wave_kernel<T, NT, TILELOG, K, INV, IN_T>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid_of(ntiles)), dim3(NT), lds, stream, a, ntiles, L2);
+  return hipGetLastError();
+}
+
+template <typename T, int NT, int TILELOG, bool INV, typename IN_T>
+static hipError_t launch_col_wave(const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  switch (L1) {
+#define NTT_COL(KK) \
+  case KK: return launch_col_wave_k<T, NT, TILELOG, KK, INV, IN_T>(a, L2, stream);
+    NTT_COL(1) NTT_COL(2) NTT_COL(3) NTT_COL(4) NTT_COL(5) NTT_COL(6) NTT_COL(7) NTT_COL(8) NTT_COL(9) NTT_COL(10)
+#undef NTT_COL
+  }
+  return hipErrorInvalidValue;
+}
+
+// Columns longer than 2^10 (transforms beyond 2^24) keep the workgroup rounds.
+hipError_t launch_col_fwd_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_col_inv_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_row_rounds(int word_bits, int kind, const PassArgs& a, int L1, int L2, hipStream_t stream);
+
+hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  if (L1 > 10) return launch_col_fwd_rounds(word_bits, a, L1, L2, stream);
+  if (word_bits == 32) {
+    if (a.in_u16) return launch_col_wave<uint32_t, 1024, 14, false, uint16_t>(a, L1, L2, stream);
+    return launch_col_wave<uint32_t, 1024, 14, false, uint32_t>(a, L1, L2, stream);
+  }
+  return launch_col_wave<uint64_t, 512, 13, false, uint64_t>(a, L1, L2, stream);
+}
+
+hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  if (L1 > 10) return launch_col_inv_rounds(word_bits, a, L1, L2, stream);
+  if (word_bits == 32) return launch_col_wave<uint32_t, 1024, 14, true, uint32_t>(a, L1, L2, stream);
+  return launch_col_wave<uint64_t, 512, 13, true, uint64_t>(a, L1, L2, stream);
+}
+
+template <typename T, int NT, int M, int KIND>
+static hipError_t launch_row_wave(const PassArgs& a, int L1, hipStream_t stream) {
+  const uint64_t nrows = (uint64_t)a.batch << L1;
+  const size_t lds = (KIND == 2 ? 2 : 1) * (size_t)lds_words(1 << M) * sizeof(T);
+  auto k = row_wave_kernel<T, NT, M, KIND>;
+  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(grid_of(nrows)), dim3(NT), lds, stream, a, nrows);
+  return hipGetLastError();
+}
+
+template <int KIND>
+static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  if (word_bits == 32 && L2 == 14) return launch_row_wave<uint32_t, 1024, 14, KIND>(a, L1, stream);
+  if (word_bits == 64 && L2 == 13) return launch_row_wave<uint64_t, 512, 13, KIND>(a, L1, stream);
+  return launch_row_rounds(word_bits, KIND, a, L1, L2, stream);
+}
+
+hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  return launch_row_kind<0>(word_bits, a, L1, L2, stream);
+}
+hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool scale_ninv, hipStream_t stream) {
+  (void)scale_ninv;  // the caller passes the twist table with n^-1 folded in when asked
+  return launch_row_kind<1>(word_bits, a, L1, L2, stream);
+}
+hipError_t launch_row_polymul(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  return launch_row_kind<2>(word_bits, a, L1, L2, stream);
+}
+
+}  // namespace nttgpu
