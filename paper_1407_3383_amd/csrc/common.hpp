@@ -35,13 +35,16 @@ struct FusedItem {
 // universal table; pass 2 (rows) twists row r (of length 2^L2) by G^j,
 // G = w_N^([r]_L1), then transforms it (Algorithm 1, steps 2 and 3).  G^j =
 // w_N^e with e = j [r]_L1 < N is read from two tables: w_N^e = lo[e & (2^B-1)] *
-// hi[e >> B].
+// hi[e >> B].  With 32-bit words the row pass reads them once per thread and row:
+// for j = q + 2^10 c, G^j = G^q * w_(2^(L-10))^(c [r]_L1 mod 2^(L-10)), the second
+// factor an entry of the universal table (same in every lane).
 template <typename T>
 struct PassConst {
   T p, p2, pinv, lazy;
   TwPair<T> ninv;     // n^-1
   TwPair<T> sigma;    // 2^bits(T) / N mod p
   uint32_t L, L1, L2, B;
+  double rcp32;       // 2^32 / p rounded: estimates Shoup companions of 32-bit residues
 };
 
 }  // namespace nttgpu

@@ -265,7 +265,8 @@ int build_plan_tables(ntt_plan* pl) {
   const int W = (int)(8 * sizeof(T));
   Blob blob;
   std::vector<TwPair<T>> tw, twi;
-  pl->LT = (uint32_t)std::max(1, std::min(L, kUniversalMaxLog));
+  // long two-pass transforms also read w_(2^(L-10)) powers from the table
+  pl->LT = (uint32_t)std::max(1, std::min(L, std::max(kUniversalMaxLog, L - 10)));
   build_universal<T>(p, pl->g, (int)pl->LT, false, tw);
   build_universal<T>(p, pl->g, (int)pl->LT, true, twi);
   const size_t o_tw = blob.add(tw.data(), tw.size() * sizeof(TwPair<T>));
@@ -310,6 +311,7 @@ int build_plan_tables(ntt_plan* pl) {
   sc.L1 = pl->L1;
   sc.L2 = pl->L2;
   sc.B = pl->B;
+  sc.rcp32 = 4294967296.0 / (double)p;
   const size_t o_sc = blob.add(&sc, sizeof(sc));
   size_t o_lo = 0, o_hi = 0, o_ilo = 0, o_ihi = 0, o_ihin = 0;
   if (pl->passes > 1) {
@@ -1101,7 +1103,7 @@ IntLayout int_layout(size_t na, size_t nb) {
     off += align256(z.lc * 4);
   }
   z.o_t = off;
-  off += align256(z.npos * 4);
+  off += align256(z.nblk * crt_block_positions() * 4);
   z.o_blk = off;
   off += align256(z.nblk * 4);
   if (z.fused) {

@@ -87,7 +87,7 @@ struct CrtArgs {
   const uint32_t* r3;
   uint64_t lc;       // number of coefficients (na + nb - 1)
   uint64_t npos;     // number of 16-bit output positions (na + nb), even-padded
-  uint32_t* t;       // workspace: npos column sums with one level of carry applied
+  uint32_t* t;       // workspace: column sums with one level of carry applied, whole blocks
   uint32_t* blk;     // workspace: per-block (generate, propagate) then carry-in
   uint32_t* c;       // output: npos / 2 limbs of 32 bits
   uint32_t p1, p2, p3;

@@ -8,169 +8,179 @@
 // below 2^64).  The number C = sum_k v_k 2^(16 k) is then normalised in three steps:
 //   1. column sums over 16-bit positions m: s_m = sum_i digit_i(v_(m-i)) < 2^18,
 //      and t_m = (s_m mod 2^16) + floor(s_(m-1) / 2^16) <= 2^16 + 3, so every carry
-//      left is 0 or 1 (generate: t_m >= 2^16, propagate: t_m = 2^16 - 1);
-//   2. a scan of the per-block (generate, propagate) pairs gives each block's carry in;
-//   3. each block scans its own positions and packs pairs of 16-bit limbs.
+//      left is 0 or 1: position m generates one (t_m >= 2^16), propagates the one
+//      it receives (t_m = 2^16 - 1) or kills it (otherwise);
+//   2. the carry into a block is decided by the nearest block below it that does not
+//      propagate: a prefix maximum of keys 2 (b + 1) + generate over such blocks;
+//   3. inside a block the same prefix maximum over positions gives each position's
+//      carry in, and pairs of 16-bit limbs are packed.
 #include "kernels.hpp"
 
 namespace nttgpu {
 
 constexpr int kCrtNT = 256;
-constexpr int kCrtPPT = 8;                        // positions per thread
-constexpr int kCrtBlock = kCrtNT * kCrtPPT;       // positions per workgroup
+constexpr int kCrtPPT = 8;                   // positions per thread
+constexpr int kCrtBlock = kCrtNT * kCrtPPT;  // positions per workgroup
+constexpr int kCrtHalo = 4;                  // coefficients below the block that reach into it
 
 int crt_block_positions() { return kCrtBlock; }
 
-__device__ __forceinline__ uint32_t shoup32(uint32_t x, uint32_t w, uint32_t ws, uint32_t p) {
-  uint32_t q = __umulhi(x, ws);
-  uint32_t r = x * w - q * p;
-  return min(r, r - p);
+// Function 8 with the final correction left out: [0, 2p) for any 32-bit x.
+__device__ __forceinline__ uint32_t shoup_lazy(uint32_t x, uint32_t w, uint32_t ws, uint32_t p) {
+  return x * w - __umulhi(x, ws) * p;
+}
+__device__ __forceinline__ uint32_t red(uint32_t x, uint32_t p) { return min(x, x - p); }
+
+// v_k from the three residues; no reduction of x1 or x2 is needed first, because
+// every Shoup input below stays under 2^32:
+//   r2 + 3 p2 - x1          with x1 < p1 < 3 p2
+//   r3 + 8 p3 - x1 - u      with x1 < p1 < 6 p3 and u = x2 p1 mod p3 in [0, 2 p3)
+__device__ __forceinline__ uint64_t garner(const CrtArgs& A, uint32_t r1, uint32_t r2, uint32_t r3) {
+  const uint32_t x1 = r1;
+  const uint32_t x2 = red(shoup_lazy(r2 + 3u * A.p2 - x1, A.c12, A.c12s, A.p2), A.p2);
+  const uint32_t u = shoup_lazy(x2, A.p1m3, A.p1m3s, A.p3);
+  const uint32_t x3 = red(shoup_lazy(r3 + 8u * A.p3 - x1 - u, A.c123, A.c123s, A.p3), A.p3);
+  return (uint64_t)x1 + (uint64_t)A.p1 * x2 + A.p1p2 * (uint64_t)x3;
 }
 
-__device__ __forceinline__ uint64_t garner(const CrtArgs& A, uint64_t k) {
-  if (k >= A.lc) return 0;
-  const uint32_t p1 = A.p1, p2 = A.p2, p3 = A.p3;
-  const uint32_t x1 = A.r1[k];
-  uint32_t x1m2 = x1;  // x1 < p1 < 4 p2 reduced below p2
-  while (x1m2 >= p2) x1m2 -= p2;
-  uint32_t d2 = A.r2[k] + p2 - x1m2;
-  d2 = min(d2, d2 - p2);
-  const uint32_t x2 = shoup32(d2, A.c12, A.c12s, p2);
-  uint32_t x1m3 = x1;
-  while (x1m3 >= p3) x1m3 -= p3;
-  uint32_t x2m3 = x2;
-  while (x2m3 >= p3) x2m3 -= p3;
-  const uint32_t t = shoup32(x2m3, A.p1m3, A.p1m3s, p3);  // x2 p1 mod p3
-  uint32_t d3 = A.r3[k] + p3 - x1m3;
-  d3 = min(d3, d3 - p3);
-  d3 = d3 + p3 - t;
-  d3 = min(d3, d3 - p3);
-  const uint32_t x3 = shoup32(d3, A.c123, A.c123s, p3);
-  return (uint64_t)x1 + (uint64_t)p1 * x2 + A.p1p2 * (uint64_t)x3;
-}
+__device__ __forceinline__ uint32_t digit(uint64_t v, int i) { return (uint32_t)(v >> (16 * i)) & 0xFFFFu; }
 
-// s_m for m in [m0 - 1, m0 + PPT): needs v_(m0-4) .. v_(m0+PPT-1).
-__device__ __forceinline__ void column_sums(const CrtArgs& A, uint64_t m0, uint32_t (&t)[kCrtPPT]) {
-  uint64_t v[kCrtPPT + 4];
+// Inclusive prefix maximum across a wave.
+__device__ __forceinline__ uint32_t wave_scan_max(uint32_t x) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int i = 0; i < kCrtPPT + 4; ++i) {
-    const int64_t k = (int64_t)m0 - 4 + i;
-    v[i] = k >= 0 ? garner(A, (uint64_t)k) : 0;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, off, 64);
+    if (lane >= off) x = max(x, y);
   }
-  uint32_t s[kCrtPPT + 1];
+  return x;
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t x) {
 #pragma unroll
-  for (int q = 0; q <= kCrtPPT; ++q) {
-    // position m = m0 - 1 + q  ->  v index (m - i) - (m0 - 4) = q + 3 - i
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc += (uint32_t)((v[q + 3 - i] >> (16 * i)) & 0xFFFF);
-    s[q] = (m0 == 0 && q == 0) ? 0u : acc;
-  }
-#pragma unroll
-  for (int q = 0; q < kCrtPPT; ++q) t[q] = (s[q + 1] & 0xFFFF) + (s[q] >> 16);
+  for (int off = 32; off > 0; off >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, off, 64));
+  return x;
 }
 
-// Carry status of a run: 0 = kill (carry out 0), 1 = generate (1), 2 = propagate.
-__device__ __forceinline__ uint32_t gp_of(uint32_t t) { return t >= 0x10000u ? 1u : (t == 0xFFFFu ? 2u : 0u); }
-__device__ __forceinline__ uint32_t gp_combine(uint32_t lo, uint32_t hi) { return hi == 2u ? lo : hi; }
+// Key of a non-propagating run ending at local position j: 2 (j + 1) + generate.
+__device__ __forceinline__ uint32_t pos_key(uint32_t t, uint32_t j) {
+  return t == 0xFFFFu ? 0u : 2u * (j + 1u) + (t >= 0x10000u ? 1u : 0u);
+}
 
+// Phase 1: Garner values of the block's coefficients (plus the 4-coefficient halo
+// below it) staged once in LDS, column sums t_m for the block's positions (stored
+// for all positions of the block: they are 0 above the product), block status.
 __global__ __launch_bounds__(kCrtNT) void crt_phase1_kernel(CrtArgs A) {
-  __shared__ uint32_t red[kCrtNT];
-  const uint64_t m0 = (uint64_t)blockIdx.x * kCrtBlock + (uint64_t)threadIdx.x * kCrtPPT;
-  uint32_t t[kCrtPPT];
-  column_sums(A, m0, t);
-  uint32_t g = 2u;
+  __shared__ uint64_t v[kCrtBlock + kCrtHalo];
+  __shared__ uint32_t wmax[kCrtNT / 64];
+  const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
+  gcptr<uint32_t> r1 = gconst<uint32_t>(A.r1);
+  gcptr<uint32_t> r2 = gconst<uint32_t>(A.r2);
+  gcptr<uint32_t> r3 = gconst<uint32_t>(A.r3);
+  // local index j <-> coefficient mb - 4 + j
+  for (int j = threadIdx.x; j < kCrtBlock + kCrtHalo; j += kCrtNT) {
+    const int64_t k = (int64_t)mb - kCrtHalo + j;
+    uint64_t x = 0;
+    if (k >= 0 && (uint64_t)k < A.lc) x = garner(A, r1[k], r2[k], r3[k]);
+    v[j] = x;
+  }
+  __syncthreads();
+  uint32_t key = 0;
+  gptr<uint32_t> t = gmut<uint32_t>(A.t);
 #pragma unroll
   for (int q = 0; q < kCrtPPT; ++q) {
-    const uint64_t m = m0 + q;
-    if (m < A.npos) {
-      A.t[m] = t[q];
-      g = gp_combine(g, gp_of(t[q]));
-    }
+    const int lp = threadIdx.x + kCrtNT * q;  // position mb + lp uses v at local lp .. lp + 4
+    const uint64_t v0 = v[lp], v1 = v[lp + 1], v2 = v[lp + 2], v3 = v[lp + 3], v4 = v[lp + 4];
+    const uint32_t s = digit(v4, 0) + digit(v3, 1) + digit(v2, 2) + digit(v1, 3);       // s_m
+    const uint32_t sp = digit(v3, 0) + digit(v2, 1) + digit(v1, 2) + digit(v0, 3);      // s_(m-1)
+    const uint32_t tm = (s & 0xFFFFu) + (sp >> 16);
+    t[mb + lp] = tm;
+    key = max(key, pos_key(tm, (uint32_t)lp));
   }
-  red[threadIdx.x] = g;
+  key = wave_max(key);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = key;
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t acc = 2u;
-    for (int i = 0; i < kCrtNT; ++i) acc = gp_combine(acc, red[i]);
-    A.blk[blockIdx.x] = acc;
+    uint32_t k = 0;
+#pragma unroll
+    for (int w = 0; w < kCrtNT / 64; ++w) k = max(k, wmax[w]);
+    // 0 kill, 1 generate, 2 propagate
+    gmut<uint32_t>(A.blk)[blockIdx.x] = k == 0 ? 2u : (k & 1u);
   }
 }
 
-// One workgroup turns the per-block statuses into carry-in bits (exclusive scan).
+// Phase 2 (one workgroup): block statuses -> carry into each block.
 __global__ __launch_bounds__(1024) void crt_phase2_kernel(CrtArgs A, uint32_t nblk) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t per = (nblk + 1023) / 1024;
+  __shared__ uint32_t wsum[16];
+  gptr<uint32_t> blk = gmut<uint32_t>(A.blk);
+  const uint32_t per = (nblk + 1023) / 1024;  // at most 8: the host caps nblk at 8192
   const uint32_t b0 = threadIdx.x * per;
-  uint32_t acc = 2u;
-  for (uint32_t i = 0; i < per; ++i)
-    if (b0 + i < nblk) acc = gp_combine(acc, A.blk[b0 + i]);
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  // inclusive Hillis-Steele scan of the thread summaries
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint32_t v = sh[threadIdx.x];
-    uint32_t lo = threadIdx.x >= (uint32_t)off ? sh[threadIdx.x - off] : 2u;
-    __syncthreads();
-    sh[threadIdx.x] = gp_combine(lo, v);
-    __syncthreads();
+  uint32_t st[8];
+  uint32_t key = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < 8; ++i) {
+    st[i] = 2u;
+    if (i < per && b0 + i < nblk) {
+      st[i] = blk[b0 + i];
+      if (st[i] != 2u) key = 2u * (b0 + i + 1u) + st[i];
+    }
   }
-  uint32_t carry = threadIdx.x == 0 ? 0u : (sh[threadIdx.x - 1] == 1u ? 1u : 0u);
+  const uint32_t incl = wave_scan_max(key);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 63) wsum[w] = incl;
   __syncthreads();
-  for (uint32_t i = 0; i < per; ++i) {
-    if (b0 + i < nblk) {
-      const uint32_t st = A.blk[b0 + i];
-      A.blk[b0 + i] = carry;
-      carry = st == 2u ? carry : (st == 1u ? 1u : 0u);
+  uint32_t below = 0;
+  for (int i = 0; i < w; ++i) below = max(below, wsum[i]);
+  const uint32_t up = (uint32_t)__shfl_up((int)incl, 1, 64);
+  uint32_t excl = max(below, lane > 0 ? up : 0u);
+#pragma unroll
+  for (uint32_t i = 0; i < 8; ++i) {
+    if (i < per && b0 + i < nblk) {
+      blk[b0 + i] = excl & 1u;  // carry in: generate bit of the nearest non-propagating block below
+      if (st[i] != 2u) excl = 2u * (b0 + i + 1u) + st[i];
     }
   }
 }
 
+// Phase 3: carry into each position from the in-block prefix maximum and the block's
+// carry in, then 16-bit limbs packed in pairs.
 __global__ __launch_bounds__(kCrtNT) void crt_phase3_kernel(CrtArgs A) {
-  __shared__ uint32_t sh[kCrtNT];
-  const uint64_t m0 = (uint64_t)blockIdx.x * kCrtBlock + (uint64_t)threadIdx.x * kCrtPPT;
-  uint32_t t[kCrtPPT];
-  uint32_t g = 2u;
+  __shared__ uint32_t wsum[kCrtNT / 64];
+  const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
+  const uint32_t lp0 = threadIdx.x * kCrtPPT;
+  const uint4* tv = (const uint4*)(A.t + mb + lp0);  // the workspace holds whole blocks
+  const uint4 ta = tv[0], tb = tv[1];
+  const uint32_t t[kCrtPPT] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+  uint32_t key = 0;
 #pragma unroll
-  for (int q = 0; q < kCrtPPT; ++q) {
-    const uint64_t m = m0 + q;
-    t[q] = m < A.npos ? A.t[m] : 0u;
-    g = gp_combine(g, gp_of(t[q]));
-  }
-  sh[threadIdx.x] = g;
+  for (int q = 0; q < kCrtPPT; ++q) key = max(key, pos_key(t[q], lp0 + q));
+  const uint32_t incl = wave_scan_max(key);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 63) wsum[w] = incl;
   __syncthreads();
-  for (int off = 1; off < kCrtNT; off <<= 1) {
-    uint32_t v = sh[threadIdx.x];
-    uint32_t lo = threadIdx.x >= (uint32_t)off ? sh[threadIdx.x - off] : 2u;
-    __syncthreads();
-    sh[threadIdx.x] = gp_combine(lo, v);
-    __syncthreads();
-  }
-  const uint32_t cin_blk = A.blk[blockIdx.x];
-  uint32_t carry;
-  if (threadIdx.x == 0) {
-    carry = cin_blk;
-  } else {
-    const uint32_t st = sh[threadIdx.x - 1];
-    carry = st == 2u ? cin_blk : (st == 1u ? 1u : 0u);
-  }
-  uint32_t limb16[kCrtPPT];
+  uint32_t below = 0;
+  for (int i = 0; i < w; ++i) below = max(below, wsum[i]);
+  const uint32_t up = (uint32_t)__shfl_up((int)incl, 1, 64);
+  const uint32_t excl = max(below, lane > 0 ? up : 0u);
+  uint32_t carry = excl == 0 ? gconst<uint32_t>(A.blk)[blockIdx.x] : (excl & 1u);
+  uint32_t limb[kCrtPPT];
 #pragma unroll
   for (int q = 0; q < kCrtPPT; ++q) {
     const uint32_t x = t[q] + carry;
-    limb16[q] = x & 0xFFFFu;
+    limb[q] = x & 0xFFFFu;
     carry = x >> 16;
   }
+  gptr<uint32_t> c = gmut<uint32_t>(A.c);
 #pragma unroll
   for (int q = 0; q < kCrtPPT; q += 2) {
-    const uint64_t m = m0 + q;
-    if (m < A.npos) A.c[m >> 1] = limb16[q] | (limb16[q + 1] << 16);
+    const uint64_t m = mb + lp0 + q;
+    if (m < A.npos) c[m >> 1] = limb[q] | (limb[q + 1] << 16);
   }
 }
 
 hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream) {
   const uint64_t nblk = (a.npos + kCrtBlock - 1) / kCrtBlock;
   if (nblk == 0) return hipSuccess;
+  if (nblk > 8192) return hipErrorInvalidValue;
   hipLaunchKernelGGL(crt_phase1_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);
   hipLaunchKernelGGL(crt_phase2_kernel, dim3(1), dim3(1024), 0, stream, a, (uint32_t)nblk);
   hipLaunchKernelGGL(crt_phase3_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);

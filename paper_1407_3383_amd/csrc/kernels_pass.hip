@@ -38,6 +38,48 @@ __device__ __forceinline__ T twist2(const Arith<T>& ar, T x, uint32_t e, int B, 
   return ar.shoup(ar.shoup(x, h.w, h.ws), l.w, l.ws);
 }
 
+// Shoup companion floor(w 2^32 / p) of a residue w < p: the double estimate is within
+// 2^-20 of the exact quotient, so one correction step makes it exact.
+__device__ __forceinline__ uint32_t companion32(uint32_t w, uint32_t p, double rcp32) {
+  uint32_t q = (uint32_t)((double)w * rcp32);
+  const int64_t r = (int64_t)((uint64_t)w << 32) - (int64_t)((uint64_t)q * p);
+  if (r < 0) --q;
+  else if (r >= (int64_t)p) ++q;
+  return q;
+}
+
+// The per-thread twist factor w_N^e = lo[e mod 2^B] * hi[e >> B] as a Shoup pair.
+__device__ __forceinline__ TwPair<uint32_t> thread_factor(const Arith<uint32_t>& ar, uint32_t e, int B,
+                                                          gcptr<TwPair<uint32_t>> lo, gcptr<TwPair<uint32_t>> hi,
+                                                          double rcp32) {
+  const TwPair<uint32_t> h = ldtw<uint32_t>(hi + (e >> B));
+  const TwPair<uint32_t> l = ldtw<uint32_t>(lo + (e & ((1u << B) - 1)));
+  TwPair<uint32_t> f;
+  f.w = ar.red1(ar.shoup(l.w, h.w, h.ws));
+  f.ws = companion32(f.w, ar.p, rcp32);
+  return f;
+}
+
+// The row's factors w_(2^S)^(c Rr mod 2^S), c < C, from the universal table
+// (t[2^(S-1) + i] = w_(2^S)^([i]_(S-1)); the upper half of the circle is its negation,
+// whose companion is the bitwise complement).  The same in every lane.
+template <int C>
+__device__ __forceinline__ void row_factors(TwPair<uint32_t> (&D)[C], gcptr<TwPair<uint32_t>> t, int S, uint32_t Rr,
+                                            uint32_t p) {
+  const uint32_t mask = (1u << S) - 1, half = 1u << (S - 1);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const uint32_t e = ((uint32_t)c * Rr) & mask;
+    const uint32_t i = brev_u(e & (half - 1), S - 1);
+    TwPair<uint32_t> x = uni(ldtw<uint32_t>(t + (half + i)));
+    if (e >= half) {
+      x.w = p - x.w;
+      x.ws = ~x.ws;
+    }
+    D[c] = x;
+  }
+}
+
 // ------------------------------------------------------------------ wave-local columns
 // Stages [T0, T0+R) of V vectors of 2^K words (K <= 10) at LDS stride vs, processed by
 // one wave: work items (vector, cluster) are spread over the 64 lanes.
@@ -152,8 +194,10 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
   __syncthreads();
 }
 
+// Two workgroups per CU (at most 64 VGPRs for 1024-thread 32-bit tiles) so that one
+// tile's HBM phases overlap the other's arithmetic.
 template <typename T, int NT, int TILELOG, int K, bool INV, typename IN_T>
-__global__ __launch_bounds__(NT) void col_wave_kernel(PassArgs A, uint64_t ntiles, int L2) {
+__global__ __launch_bounds__(NT, (NT == 1024 ? 8 : 4)) void col_wave_kernel(PassArgs A, uint64_t ntiles, int L2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
   const Arith<T> ar = arith_uni<T>(A.pc);
@@ -176,6 +220,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
   const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
   const int L1 = (int)uni(pc->L1);
   const int B = (int)uni(pc->B);
+  const int S = (int)uni(pc->L) - 10;
+  const double rcp32 = pc->rcp32;
   const uint64_t vec = rowid >> L1;
   const uint32_t r = (uint32_t)(rowid & ((1u << L1) - 1));
   const uint32_t Rr = brev_u(r, L1);
@@ -195,6 +241,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
     const gcptr<T> inb = gconst<T>(uni(A.in2)) + vec * A.in_stride + off;
     TwPair<T> wf[C > 1 ? C - 1 : 1];
     if constexpr (R > 0) cluster_twiddles<T, R, true>(wf, tw, 0, 0, 0u, 0u);
+    TwPair<T> D[C];
+    if constexpr (sizeof(T) == 4) row_factors<C>(D, tw, S, Rr, ar.p);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int q = t0 + i * NT;
@@ -206,11 +254,20 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
         v[0][cc] = ina[j];
         if constexpr (KIND == 2) v[1][cc] = inb[j];
       }
+      if constexpr (sizeof(T) == 4) {
+        const TwPair<T> V = thread_factor(ar, (uint32_t)q * Rr, B, lo, hi, rcp32);
 #pragma unroll
-      for (int cc = 0; cc < C; ++cc) {
-        const uint32_t e = (uint32_t)(q + 1024 * cc) * Rr;
-        v[0][cc] = twist2(ar, v[0][cc], e, B, lo, hi);
-        if constexpr (KIND == 2) v[1][cc] = twist2(ar, v[1][cc], e, B, lo, hi);
+        for (int cc = 0; cc < C; ++cc) {
+          v[0][cc] = ar.shoup(ar.shoup(v[0][cc], V.w, V.ws), D[cc].w, D[cc].ws);
+          if constexpr (KIND == 2) v[1][cc] = ar.shoup(ar.shoup(v[1][cc], V.w, V.ws), D[cc].w, D[cc].ws);
+        }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const uint32_t e = (uint32_t)(q + 1024 * cc) * Rr;
+          v[0][cc] = twist2(ar, v[0][cc], e, B, lo, hi);
+          if constexpr (KIND == 2) v[1][cc] = twist2(ar, v[1][cc], e, B, lo, hi);
+        }
       }
       if constexpr (R > 0) cluster_fwd<T, LAZY, R, NV>(ar, v, 0, wf);
       const int lb0 = lidx(q);
@@ -276,6 +333,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
     const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride + off;
     TwPair<T> wi[C > 1 ? C - 1 : 1];
     if constexpr (R > 0) cluster_twiddles<T, R, true>(wi, twi, 0, 0, 0u, 0u);
+    TwPair<T> Di[C];
+    if constexpr (sizeof(T) == 4) row_factors<C>(Di, twi, S, Rr, ar.p);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int q = t0 + i * NT;
@@ -284,12 +343,22 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
       if constexpr (R > 0) cluster_inv<T, LAZY, R>(ar, v, wi);
+      if constexpr (sizeof(T) == 4) {
+        const TwPair<T> V = thread_factor(ar, (uint32_t)q * Rr, B, ilo, ihi, rcp32);
 #pragma unroll
-      for (int cc = 0; cc < C; ++cc) {
-        const uint32_t j = (uint32_t)(q + 1024 * cc);
-        T y = twist2(ar, v[cc], j * Rr, B, ilo, ihi);
-        if constexpr (!LAZY) y = ar.red1(y);
-        out[j] = y;
+        for (int cc = 0; cc < C; ++cc) {
+          T y = ar.shoup(ar.shoup(v[cc], V.w, V.ws), Di[cc].w, Di[cc].ws);
+          if constexpr (!LAZY) y = ar.red1(y);
+          out[q + 1024 * cc] = y;
+        }
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const uint32_t j = (uint32_t)(q + 1024 * cc);
+          T y = twist2(ar, v[cc], j * Rr, B, ilo, ihi);
+          if constexpr (!LAZY) y = ar.red1(y);
+          out[j] = y;
+        }
       }
     }
     __syncthreads();
@@ -297,7 +366,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 }
 
 template <typename T, int NT, int M, int KIND>
-__global__ __launch_bounds__(NT) void row_wave_kernel(PassArgs A, uint64_t nrows) {
+__global__ __launch_bounds__(NT, (KIND == 2 ? 1 : (NT == 1024 ? 8 : 4))) void row_wave_kernel(PassArgs A, uint64_t nrows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
   T* sb = sa + lds_words(1 << M);
