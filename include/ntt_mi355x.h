@@ -171,6 +171,28 @@ int polymul_batch_launch(const ntt_batch* batch, void* workspace, size_t ws_byte
 /* NULL is accepted; the caller makes sure no launch of the batch is still pending. */
 int polymul_batch_destroy(ntt_batch* batch);
 
+/* ---------------------------------------------------------------- HIP graphs
+ * Launch-bound callers (many small products, a serving loop) replay a recorded
+ * sequence of library calls as one graph launch instead of issuing every kernel.
+ * ntt_graph_begin starts recording `hip_stream` (a created stream, not the null
+ * stream; thread-local capture mode); every library call made on that stream by
+ * this thread until ntt_graph_end is recorded, not run.  ntt_graph_end closes the
+ * recording and instantiates it.  A replay (ntt_graph_launch) reruns the recorded
+ * kernels on the same device pointers, reading whatever the buffers hold then.
+ * Recordable: polymul_batch_launch, intmul_crt, polymul_modp, ntt_forward and
+ * ntt_inverse without NTT_VALIDATE, once the plans they use exist (run each call
+ * once before recording it).  Refused with NTT_EINVAL while recording (nothing is
+ * enqueued, the recording stays usable): calls that would create a plan, allocate,
+ * copy host data (polymul_modp_batch) or wait (NTT_VALIDATE).  Recorded graphs hold
+ * no memset nodes.  The caller owns the graph and destroys it once no replay is
+ * pending.  Errors: NTT_EINVAL, NTT_EDEVICE (the HIP capture or instantiation
+ * failed, e.g. because another call on the stream was not recordable). */
+typedef struct ntt_graph ntt_graph;
+int ntt_graph_begin(void* hip_stream);
+int ntt_graph_end(void* hip_stream, ntt_graph** out);
+int ntt_graph_launch(const ntt_graph* graph, void* hip_stream);
+int ntt_graph_destroy(ntt_graph* graph);
+
 /* ---------------------------------------------------------------- integer product
  * Section 5.3: Kronecker segmentation with 16-bit chunks (A(2^16) = a) and the
  * three-prime transform over p1 = 998244353, p2 = 469762049, p3 = 167772161,

@@ -38,6 +38,16 @@ int ok() {
   return NTT_OK;
 }
 
+// Set between ntt_graph_begin and ntt_graph_end on the capturing thread: calls that
+// would allocate, copy from the host or wait are refused meanwhile.
+thread_local bool g_capturing = false;
+
+bool capturing(hipStream_t s) {
+  if (g_capturing) return true;
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -361,6 +371,9 @@ int check_modulus(uint64_t p, int* l_out) {
 }
 
 int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags) {
+  if (g_capturing)
+    return fail(NTT_EINVAL, "plan for p = %llu, N = 2^%u does not exist yet and cannot be created during a graph "
+                "capture: run the call once before capturing it", (unsigned long long)p, log2n);
   int l = 0;
   int rc = check_modulus(p, &l);
   if (rc) return rc;
@@ -464,6 +477,9 @@ int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out) {
 // staging slot; the slot is reused only after the copy that used it has completed.
 int upload(DeviceCtx* c, void* dst, const void* src, size_t bytes, hipStream_t stream) {
   if (bytes == 0) return NTT_OK;
+  if (capturing(stream))
+    return fail(NTT_EINVAL, "this call copies host descriptors and cannot be captured in a graph: "
+                "use a polymul_batch_create handle");
   std::lock_guard<std::mutex> lk(c->mu);
   Staging& s = c->ring[c->next++ % 8];
   if (s.pending) {
@@ -491,6 +507,7 @@ bool aligned_to(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
 // Synchronous check that every element of `batch` vectors is < p (NTT_VALIDATE).
 int validate_range(int wb, const void* x, size_t n, size_t stride, size_t batch, uint64_t p, hipStream_t stream) {
+  if (capturing(stream)) return fail(NTT_EINVAL, "NTT_VALIDATE waits for the device and cannot be captured in a graph");
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   DeviceCtx* c = device_ctx(dev);
@@ -870,6 +887,9 @@ size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count) {
 int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes, void* hip_stream) {
   try {
     hipStream_t stream = (hipStream_t)hip_stream;
+    if (capturing(stream))
+      return fail(NTT_EINVAL, "polymul_modp_batch copies host descriptors and cannot be captured in a graph: "
+                  "use a polymul_batch_create handle");
     if (count == 0) return ok();
     if (!d) return fail(NTT_EINVAL, "descriptor array is NULL");
     std::vector<ProductShape> shapes(count);
@@ -965,6 +985,7 @@ int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t coun
   try {
     if (!out) return fail(NTT_EINVAL, "out is NULL");
     *out = nullptr;
+    if (g_capturing) return fail(NTT_EINVAL, "polymul_batch_create allocates and cannot run during a graph capture");
     if (count && !d) return fail(NTT_EINVAL, "descriptor array is NULL");
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -1070,6 +1091,66 @@ int polymul_batch_destroy(ntt_batch* bt) {
   if (!bt) return ok();
   if (bt->ditems) (void)hipFree(bt->ditems);
   delete bt;
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------- graphs
+struct ntt_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+extern "C" {
+
+int ntt_graph_begin(void* hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (!s) return fail(NTT_EINVAL, "graph capture needs a created stream, not the null stream");
+  if (g_capturing) return fail(NTT_EINVAL, "a capture is already open on this thread");
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  g_capturing = true;
+  return ok();
+}
+
+int ntt_graph_end(void* hip_stream, ntt_graph** out) {
+  if (!out) return fail(NTT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g_capturing) return fail(NTT_EINVAL, "no capture is open on this thread");
+  g_capturing = false;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || !g) return fail(NTT_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(NTT_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  ntt_graph* G = new ntt_graph();
+  G->graph = g;
+  G->exec = x;
+  (void)hipGetDevice(&G->device);
+  *out = G;
+  return ok();
+}
+
+int ntt_graph_launch(const ntt_graph* g, void* hip_stream) {
+  if (!g) return fail(NTT_EINVAL, "graph is NULL");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device) return fail(NTT_EINVAL, "graph belongs to device %d, current device is %d", g->device, dev);
+  HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)hip_stream));
+  return ok();
+}
+
+int ntt_graph_destroy(ntt_graph* g) {
+  if (!g) return ok();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return ok();
 }
 

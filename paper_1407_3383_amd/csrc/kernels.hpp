@@ -81,6 +81,11 @@ hipError_t launch_range_check(int word_bits, const void* x, uint64_t n, uint64_t
                               uint32_t* flag, hipStream_t stream);
 
 // Integer product: Garner reconstruction + carry propagation into 32-bit limbs.
+// Raises a kernel's dynamic-LDS limit to `bytes` the first time a launch needs it
+// (the attribute is process-wide), so repeated and graph-captured launches make no
+// attribute call.
+hipError_t allow_dynamic_lds(const void* kernel, size_t bytes);
+
 struct CrtArgs {
   const uint32_t* r1;
   const uint32_t* r2;

@@ -11,9 +11,23 @@
 //       step 4.  The inverse runs the mirror sequence with G^-j.
 //   A fused row pass serves the polynomial product: twist, forward both operands,
 //   entry-wise product, inverse, inverse twist, all in LDS.
+#include <mutex>
+#include <unordered_map>
+
 #include "kernels.hpp"
 
 namespace nttgpu {
+
+hipError_t allow_dynamic_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> granted;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t& g = granted[kernel];
+  if (bytes <= g) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) g = bytes;
+  return e;
+}
 
 __device__ __forceinline__ uint32_t brev_bits(uint32_t i, int L) { return L == 0 ? 0u : (__brev(i) >> (32 - L)); }
 
@@ -91,12 +105,12 @@ static hipError_t launch_lds_cls(bool inverse, const LdsNttArgs& a, hipStream_t 
   const int grid = (int)(a.batch < 65536u ? a.batch : 65536u);
   if (inverse) {
     auto k = lds_ntt_kernel<T, NT, LOGS, true>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, stream, a);
   } else {
     auto k = lds_ntt_kernel<T, NT, LOGS, false>;
-    hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = allow_dynamic_lds((const void*)k, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, stream, a);
   }
@@ -333,7 +347,7 @@ static hipError_t launch_col_t(const PassArgs& a, int L1, int L2, hipStream_t st
   const uint64_t ntiles = (uint64_t)a.batch << (L2 - LC);
   const size_t lds = (size_t)(1 << LC) * (lds_words(1 << L1) + 1) * sizeof(T);
   auto k = col_kernel<T, NT, TILELOG, INV, IN_T>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid_for(ntiles)), dim3(NT), lds, stream, a, ntiles);
   return hipGetLastError();
@@ -357,7 +371,7 @@ static hipError_t launch_row_t(const PassArgs& a, int L1, int L2, hipStream_t st
   const uint64_t nrows = (uint64_t)a.batch << L1;
   const size_t lds = (KIND == 2 ? 2 : 1) * (size_t)lds_words(1 << L2) * sizeof(T);
   auto k = row_kernel<T, NT, KIND>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid_for(nrows)), dim3(NT), lds, stream, a, nrows);
   return hipGetLastError();

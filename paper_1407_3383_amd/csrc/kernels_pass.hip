@@ -388,7 +388,7 @@ static hipError_t launch_col_wave_k(const PassArgs& a, int L2, hipStream_t strea
   const uint64_t ntiles = (uint64_t)a.batch << (L2 - LC);
   const size_t lds = (size_t)(1 << LC) * (lds_words(1 << K) + 1) * sizeof(T);
   auto k = col_wave_kernel<T, NT, TILELOG, K, INV, IN_T>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid_of(ntiles)), dim3(NT), lds, stream, a, ntiles, L2);
   return hipGetLastError();
@@ -430,7 +430,7 @@ static hipError_t launch_row_wave(const PassArgs& a, int L1, hipStream_t stream)
   const uint64_t nrows = (uint64_t)a.batch << L1;
   const size_t lds = (KIND == 2 ? 2 : 1) * (size_t)lds_words(1 << M) * sizeof(T);
   auto k = row_wave_kernel<T, NT, M, KIND>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid_of(nrows)), dim3(NT), lds, stream, a, nrows);
   return hipGetLastError();

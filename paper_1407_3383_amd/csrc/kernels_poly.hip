@@ -447,7 +447,7 @@ template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
 static hipError_t launch_fused_cls(const FusedBatch& batch, int grid, hipStream_t stream) {
   const size_t lds = 2 * (size_t)lds_words(1 << LOGS) * sizeof(T);
   auto k = polymul_fused_kernel<T, NT, LOGS, LMIN, MAXD, PM>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, stream, batch);
   return hipGetLastError();

@@ -41,6 +41,7 @@ EXPORTS = (
     "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt",
+    "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
 )
 
 
@@ -98,6 +99,10 @@ def load(path: str = LIB_PATH):
         "polymul_batch_destroy": (ci, [vp]),
         "intmul_workspace_bytes": (sz, [sz, sz]),
         "intmul_crt": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
+        "ntt_graph_begin": (ci, [vp]),
+        "ntt_graph_end": (ci, [vp, ctypes.POINTER(vp)]),
+        "ntt_graph_launch": (ci, [vp, vp]),
+        "ntt_graph_destroy": (ci, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -186,7 +191,7 @@ def _res_dtype(p: int):
 
 # ----------------------------------------------------------------------------- products
 
-def polymul(a, b, p: int, out=None, stream=None):
+def polymul(a, b, p: int, out=None, stream=None, workspace=None):
     """c = a * b mod p (linear product, len(a) + len(b) - 1 coefficients)."""
     torch = _torch()
     L = load()
@@ -194,7 +199,8 @@ def polymul(a, b, p: int, out=None, stream=None):
     lc = la + lb - 1 if la and lb else 0
     if out is None:
         out = torch.empty(lc, dtype=_res_dtype(p), device=a.device)
-    ws = _workspace(L.polymul_workspace_bytes(p, la, lb), a.device)
+    need = L.polymul_workspace_bytes(p, la, lb)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, a.device)
     _check(L.polymul_modp(p, _ptr(a), la, _ptr(b), lb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                           _stream(stream)), "polymul_modp")
     return out
@@ -299,7 +305,7 @@ class Batch:
             pass
 
 
-def intmul(a16, b16, out=None, stream=None):
+def intmul(a16, b16, out=None, stream=None, workspace=None):
     """Product of two little-endian 16-bit-limb integers -> ceil((na+nb)/2) 32-bit limbs."""
     torch = _torch()
     L = load()
@@ -307,10 +313,53 @@ def intmul(a16, b16, out=None, stream=None):
     nc = (na + nb + 1) // 2
     if out is None:
         out = torch.empty(nc, dtype=torch.int32, device=a16.device)
-    ws = _workspace(L.intmul_workspace_bytes(na, nb), a16.device)
+    need = L.intmul_workspace_bytes(na, nb)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, a16.device)
     _check(L.intmul_crt(_ptr(a16), na, _ptr(b16), nb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                         _stream(stream)), "intmul_crt")
     return out
+
+
+# ----------------------------------------------------------------------------- graphs
+
+class Graph:
+    """Records the library calls made on `stream` inside a `with` block as one HIP
+    graph (ntt_graph_begin / ntt_graph_end); `replay()` reruns them.  Allocate every
+    output and workspace before the block, and run each call once before recording
+    it so that its plans exist."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.handle = None
+
+    def __enter__(self):
+        _check(load().ntt_graph_begin(_stream(self.stream)), "ntt_graph_begin")
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = ctypes.c_void_p()
+        rc = load().ntt_graph_end(_stream(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(rc, "ntt_graph_end")
+        self.handle = h if rc == NTT_OK else None
+        return False
+
+    def replay(self, stream=None):
+        if self.handle is None:
+            raise RuntimeError("graph was not recorded")
+        _check(load().ntt_graph_launch(self.handle, _stream(stream if stream is not None else self.stream)),
+               "ntt_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ntt_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------------------- transforms
