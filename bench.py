@@ -35,10 +35,36 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # multiplicand twiddle: 3 multiplies + 1 subtraction (Function 8 without the final
 # correction) and 5 add/sub/min for the lazy sum and difference.
 OPS_PER_BFLY = 9
+# HBM bytes per launch of the fused kernel at the default workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy's readings; valid only
+# while the kernel's sources are the ones that were measured.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "polymul_fused_kernel_batch1024_n65536.md")
+KERNEL_SOURCES = ["arith.hpp", "common.hpp", "kernels.hpp", "ntt_lds.hpp", "ntt_wave.hpp", "kernels_poly.hip"]
 
 
 def log(msg: str):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """(bytes per launch, None) from the committed counter summary, or (None, reason)."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None, "no counter summary"
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    hsh = re.search(r"^kernel_sources_sha256: ([0-9a-f]+)", text, re.M)
+    if not t or not hsh:
+        return None, "counter summary without figures"
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1407_3383_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != hsh.group(1):
+        return None, "kernel changed since the counters were taken"
+    return int(t.group(1)), None
 
 
 def main() -> int:
@@ -147,6 +173,7 @@ def main() -> int:
         },
     }
     achieved_tops = bfly_per_step * OPS_PER_BFLY / (kern_ms * 1e-3) / 1e12
+    traffic, why = measured_traffic() if (items, args.log2len) == (1024, 15) else (None, "not the profiled workload")
     out["roofline"] = {
         "bound": "alu",
         "kernel": "polymul_fused_kernel<u32, 1024 threads, 2^14-word sub-problems>",
@@ -154,9 +181,14 @@ def main() -> int:
         "peak": round(ALU_PEAK_TOPS, 3),
         "unit": "Tops/s (32-bit integer lane operations, %d per butterfly)" % OPS_PER_BFLY,
         "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
-        "traffic": None,
+        "traffic": traffic,
         "kernel_ms": round(kern_ms, 4),
     }
+    if traffic is None:
+        out["roofline"]["traffic_note"] = why
+    else:
+        out["roofline"]["traffic_note"] = ("HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                                           "%.2fx the algorithmic bytes)" % (traffic / alg_bytes))
 
     if not args.no_percall:
         log("per-call baseline: %d separate polymul_modp launches x %d steps" % (items, args.percall_steps))

@@ -59,6 +59,7 @@ typedef struct {
   uint32_t word_bits; /* 32 or 64: element type of the plan's vectors         */
   uint32_t flags;     /* NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE        */
   uint32_t passes;    /* number of HBM passes of one transform (1 = LDS-resident) */
+  uint32_t row_log2;  /* two passes: rows of 2^row_log2 words, columns of n / 2^row_log2 */
 } ntt_plan_info;
 
 /* Polynomial-product descriptor for the batched entry point.  a, b, c are device
@@ -170,6 +171,33 @@ size_t polymul_batch_launch_workspace_bytes(const ntt_batch* batch);
 int polymul_batch_launch(const ntt_batch* batch, void* workspace, size_t ws_bytes, void* hip_stream);
 /* NULL is accepted; the caller makes sure no launch of the batch is still pending. */
 int polymul_batch_destroy(ntt_batch* batch);
+
+/* ---------------------------------------------------------------- tuning
+ * Launch-shape choices the kernels support, picked per size by the autotuner that
+ * ships with the Python package (it times every candidate on the device, checks
+ * that all candidates give identical results and writes a text file of choices).
+ * Keys and values:
+ *   "split.w32.L<L>"  (15 <= L <= 26) row length log2 of two-pass transform plans
+ *                     created by ntt_plan_create: 12, 13 or 14 (default 14)
+ *   "split.w64.L<L>"  (14 <= L <= 26) the same for 64-bit primes: 12 or 13 (default 13)
+ *   "psplit.w32.L<L>", "psplit.w64.L<L>"  the same for the plans the products cache
+ *   "fused.single.max.w32"  largest log2 N at which a single product (polymul_modp,
+ *                     each prime of intmul_crt) takes the fused one-workgroup kernel:
+ *                     14, 15 or 16 (default 16); above it the two-pass path (batches
+ *                     keep the fused kernel up to 2^16)
+ *   "fused.single.max.w64"  the same for 64-bit primes: 13, 14 or 15 (default 15)
+ * A choice applies to plans created afterwards: clear the plan cache to re-plan.
+ * Every choice computes the same (unique, canonical) results.
+ * ntt_tune_set / ntt_tune_get: NTT_EINVAL for an unknown key, a value out of range
+ * or (get) a key that is not set.  ntt_tune_load reads "key value" lines ('#'
+ * starts a comment) and applies all of them or, on any bad line, none (NTT_EINVAL).
+ * ntt_plan_cache_clear destroys the cached plans of the current device (waits for
+ * the device); batch handles and graphs made before it must not be used again. */
+int ntt_tune_set(const char* key, int64_t value);
+int ntt_tune_get(const char* key, int64_t* value);
+int ntt_tune_clear(void);
+int ntt_tune_load(const char* path);
+int ntt_plan_cache_clear(void);
 
 /* ---------------------------------------------------------------- HIP graphs
  * Launch-bound callers (many small products, a serving loop) replay a recorded

@@ -48,6 +48,47 @@ bool capturing(hipStream_t s) {
   return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
 }
 
+// ============================================================================ tuning choices
+// Values chosen by the autotuner (or set by hand) that override the built-in
+// defaults.  Keys:
+//   split.w<W>.L<L>   row length 2^L2 of two-pass transform plans of length 2^L
+//   psplit.w<W>.L<L>  the same for the plans the products use
+//   fused.single.max.w<W>  largest log2 N of a single product served by the fused
+//                     one-workgroup kernel
+std::mutex g_tune_mu;
+std::map<std::string, int64_t> g_tune;
+
+// Range check of one (key, value); returns false for an unknown key or a value the
+// kernels do not implement.
+bool tune_valid(const std::string& key, int64_t v) {
+  int w = 0, L = 0;
+  char tail = 0;
+  if (sscanf(key.c_str(), "split.w%d.L%d%c", &w, &L, &tail) == 2 ||
+      sscanf(key.c_str(), "psplit.w%d.L%d%c", &w, &L, &tail) == 2) {
+    if (w == 32) return L >= 15 && L <= 26 && v >= 12 && v <= 14;
+    if (w == 64) return L >= 14 && L <= 26 && v >= 12 && v <= 13;
+    return false;
+  }
+  if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
+    if (w == 32) return v >= 14 && v <= 16;
+    if (w == 64) return v >= 13 && v <= 15;
+  }
+  return false;
+}
+
+int64_t tune_value(const std::string& key, int64_t dflt) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  return it == g_tune.end() ? dflt : it->second;
+}
+
+std::string tune_key(const char* prefix, int wb, int L) {
+  char buf[64];
+  if (L >= 0) snprintf(buf, sizeof(buf), "%s.w%d.L%d", prefix, wb, L);
+  else snprintf(buf, sizeof(buf), "%s.w%d", prefix, wb);
+  return buf;
+}
+
 #define HIP_TRY(expr)                                                                        \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
@@ -370,7 +411,7 @@ int check_modulus(uint64_t p, int* l_out) {
   return NTT_OK;
 }
 
-int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags) {
+int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags, bool product = false) {
   if (g_capturing)
     return fail(NTT_EINVAL, "plan for p = %llu, N = 2^%u does not exist yet and cannot be created during a graph "
                 "capture: run the call once before capturing it", (unsigned long long)p, log2n);
@@ -404,7 +445,7 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
     pl->L2 = log2n;
   } else {
     pl->passes = 2;
-    pl->L2 = (uint32_t)pass_max_row_log2(wb);
+    pl->L2 = (uint32_t)tune_value(tune_key(product ? "psplit" : "split", wb, (int)log2n), pass_max_row_log2(wb));
     pl->L1 = log2n - pl->L2;
   }
   pl->B = (log2n + 1) / 2;
@@ -466,7 +507,7 @@ int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out) {
     return NTT_OK;
   }
   ntt_plan* pl = nullptr;
-  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN);
+  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, true);
   if (rc) return rc;
   c->plans[key] = pl;
   *out = pl;
@@ -671,6 +712,7 @@ int ntt_plan_get_info(const ntt_plan* plan, ntt_plan_info* info) {
   info->word_bits = plan->wbits;
   info->flags = plan->flags;
   info->passes = plan->passes;
+  info->row_log2 = plan->passes > 1 ? plan->L2 : 0;
   return ok();
 }
 
@@ -711,6 +753,11 @@ struct ProductShape {
   bool fused;   // one workgroup per product
   size_t lc;
 };
+
+// Largest log2 N for which a single product (polymul_modp, each prime of intmul_crt)
+// takes the fused one-workgroup kernel; above it the two-pass path.  Batches always
+// take the fused kernel up to its limit.
+int fused_limit(int wb) { return (int)tune_value(tune_key("fused.single.max", wb, -1), fused_max_log2n(wb)); }
 
 int shape_of(uint64_t p, size_t la, size_t lb, ProductShape* s) {
   int l = 0;
@@ -833,6 +880,7 @@ size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
   if (la == 0 || lb == 0) return 0;
   ProductShape s;
   if (shape_of(p, la, lb, &s)) return 0;
+  s.fused = s.L <= fused_limit(s.wb);
   return single_product_ws(s, current_cus());
 }
 
@@ -845,6 +893,7 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     ProductShape s;
     int rc = shape_of(p, la, lb, &s);
     if (rc) return rc;
+    s.fused = s.L <= fused_limit(s.wb);
     const size_t esz = s.wb / 8;
     if (!aligned_to(a, esz) || !aligned_to(b, esz) || !aligned_to(c, esz))
       return fail(NTT_EINVAL, "operands must be %zu-byte aligned", esz);
@@ -1096,6 +1145,74 @@ int polymul_batch_destroy(ntt_batch* bt) {
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------- tuning
+extern "C" {
+
+int ntt_tune_set(const char* key, int64_t value) {
+  if (!key) return fail(NTT_EINVAL, "key is NULL");
+  if (!tune_valid(key, value)) return fail(NTT_EINVAL, "unknown tuning key or value out of range: %s = %lld", key,
+                                           (long long)value);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = value;
+  return ok();
+}
+
+int ntt_tune_get(const char* key, int64_t* value) {
+  if (!key || !value) return fail(NTT_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return fail(NTT_EINVAL, "tuning key %s is not set", key);
+  *value = it->second;
+  return ok();
+}
+
+int ntt_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return ok();
+}
+
+int ntt_tune_load(const char* path) {
+  if (!path) return fail(NTT_EINVAL, "path is NULL");
+  FILE* f = fopen(path, "r");
+  if (!f) return fail(NTT_EINVAL, "cannot open %s", path);
+  char line[256];
+  int lineno = 0;
+  std::vector<std::pair<std::string, int64_t>> kv;
+  while (fgets(line, sizeof(line), f)) {
+    ++lineno;
+    char* hash = strchr(line, '#');
+    if (hash) *hash = 0;
+    char key[128];
+    long long v = 0;
+    char extra[8];
+    const int n = sscanf(line, "%127s %lld %7s", key, &v, extra);
+    if (n <= 0) continue;
+    if (n != 2 || !tune_valid(key, v)) {
+      fclose(f);
+      return fail(NTT_EINVAL, "%s:%d: not a valid 'key value' tuning line", path, lineno);
+    }
+    kv.emplace_back(key, (int64_t)v);
+  }
+  fclose(f);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : kv) g_tune[e.first] = e.second;
+  return ok();
+}
+
+int ntt_plan_cache_clear(void) {
+  if (g_capturing) return fail(NTT_EINVAL, "cannot clear plans during a graph capture");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceCtx* c = device_ctx(dev);
+  std::lock_guard<std::mutex> lk(c->mu);
+  for (auto& e : c->plans) ntt_plan_destroy(e.second);
+  c->plans.clear();
+  return ok();
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------------------- graphs
 struct ntt_graph {
   hipGraph_t graph = nullptr;
@@ -1177,7 +1294,7 @@ IntLayout int_layout(size_t na, size_t nb) {
   z.N = (size_t)1 << z.L;
   z.npos = (na + nb + 1) & ~(size_t)1;
   z.nblk = (z.npos + crt_block_positions() - 1) / crt_block_positions();
-  z.fused = z.L <= fused_max_log2n(32);
+  z.fused = z.L <= fused_limit(32);
   size_t off = 0;
   for (int i = 0; i < 3; ++i) {
     z.o_r[i] = off;

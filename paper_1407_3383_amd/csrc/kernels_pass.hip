@@ -366,7 +366,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 }
 
 template <typename T, int NT, int M, int KIND>
-__global__ __launch_bounds__(NT, (KIND == 2 ? 1 : (NT == 1024 ? 8 : 4))) void row_wave_kernel(PassArgs A, uint64_t nrows) {
+__global__ __launch_bounds__(NT, (KIND == 2 ? (sizeof(T) == 4 && NT < 1024 ? 4 : 1) : (sizeof(T) == 4 ? 8 : 4)))
+void row_wave_kernel(PassArgs A, uint64_t nrows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
   T* sb = sa + lds_words(1 << M);
@@ -436,10 +437,17 @@ static hipError_t launch_row_wave(const PassArgs& a, int L1, hipStream_t stream)
   return hipGetLastError();
 }
 
+// Rows of 2^12 .. 2^14 words (the split is a tuning choice): one wave per 1024-word block.
 template <int KIND>
 static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  if (word_bits == 32 && L2 == 14) return launch_row_wave<uint32_t, 1024, 14, KIND>(a, L1, stream);
-  if (word_bits == 64 && L2 == 13) return launch_row_wave<uint64_t, 512, 13, KIND>(a, L1, stream);
+  if (word_bits == 32) {
+    if (L2 == 14) return launch_row_wave<uint32_t, 1024, 14, KIND>(a, L1, stream);
+    if (L2 == 13) return launch_row_wave<uint32_t, 512, 13, KIND>(a, L1, stream);
+    if (L2 == 12) return launch_row_wave<uint32_t, 256, 12, KIND>(a, L1, stream);
+  } else {
+    if (L2 == 13) return launch_row_wave<uint64_t, 512, 13, KIND>(a, L1, stream);
+    if (L2 == 12) return launch_row_wave<uint64_t, 256, 12, KIND>(a, L1, stream);
+  }
   return launch_row_rounds(word_bits, KIND, a, L1, L2, stream);
 }
 

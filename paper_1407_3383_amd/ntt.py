@@ -19,6 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
+# Launch-shape choices written by the autotuner for this GPU; loaded with the library.
+# NTT_TUNE_FILE names another file, or (empty) none.
+TUNE_FILE = os.path.join(_HERE, "tuning", "gfx950.txt")
 
 NTT_OK = 0
 NTT_EINVAL = -1
@@ -41,6 +44,7 @@ EXPORTS = (
     "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt",
+    "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
 )
 
@@ -59,7 +63,8 @@ class PolymulDesc(ctypes.Structure):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("p", ctypes.c_uint64), ("g", ctypes.c_uint64), ("w", ctypes.c_uint64),
                 ("w_inv", ctypes.c_uint64), ("n_inv", ctypes.c_uint64), ("log2n", ctypes.c_uint32),
-                ("word_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("passes", ctypes.c_uint32)]
+                ("word_bits", ctypes.c_uint32), ("flags", ctypes.c_uint32), ("passes", ctypes.c_uint32),
+                ("row_log2", ctypes.c_uint32)]
 
 
 _lib = None
@@ -99,6 +104,11 @@ def load(path: str = LIB_PATH):
         "polymul_batch_destroy": (ci, [vp]),
         "intmul_workspace_bytes": (sz, [sz, sz]),
         "intmul_crt": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
+        "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
+        "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
+        "ntt_tune_clear": (ci, []),
+        "ntt_tune_load": (ci, [ctypes.c_char_p]),
+        "ntt_plan_cache_clear": (ci, []),
         "ntt_graph_begin": (ci, [vp]),
         "ntt_graph_end": (ci, [vp, ctypes.POINTER(vp)]),
         "ntt_graph_launch": (ci, [vp, vp]),
@@ -108,6 +118,11 @@ def load(path: str = LIB_PATH):
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    tune_file = os.environ.get("NTT_TUNE_FILE", TUNE_FILE)
+    if tune_file and os.path.exists(tune_file):
+        rc = L.ntt_tune_load(tune_file.encode())
+        if rc != NTT_OK:
+            raise NTTError(rc, "ntt_tune_load", L.ntt_last_error().decode())
     _lib = L
     return L
 
@@ -140,6 +155,27 @@ def find_prime(bits: int, l: int) -> int:
 
 def word_bits(p: int) -> int:
     return 32 if p < (1 << 31) else 64
+
+
+def tune_set(key: str, value: int):
+    _check(load().ntt_tune_set(key.encode(), value), "ntt_tune_set")
+
+
+def tune_get(key: str) -> Optional[int]:
+    v = ctypes.c_int64()
+    return int(v.value) if load().ntt_tune_get(key.encode(), ctypes.byref(v)) == NTT_OK else None
+
+
+def tune_clear():
+    _check(load().ntt_tune_clear(), "ntt_tune_clear")
+
+
+def tune_load(path: str):
+    _check(load().ntt_tune_load(path.encode()), "ntt_tune_load")
+
+
+def plan_cache_clear():
+    _check(load().ntt_plan_cache_clear(), "ntt_plan_cache_clear")
 
 
 # ----------------------------------------------------------------------------- tensors
