@@ -3,7 +3,7 @@
 The choices (keys of ``ntt_tune_set``, see include/ntt_mi355x.h):
 
 * ``split.w<W>.L<L>``: row length 2^L2 of a two-pass transform of length 2^L
-  (Algorithm 1 with n1 = 2^(L-L2) columns of ... rows of 2^L2 words): 12, 13 or 14
+  (Algorithm 1 read as 2^(L-L2) rows of 2^L2 words): 12, 13 or 14
   for 32-bit primes, 12 or 13 for 64-bit ones.  Shorter rows give more workgroups
   per CU in the row pass but longer columns in the column pass.
 * ``psplit.w<W>.L<L>``: the same for the plans of the products (the row pass there is
