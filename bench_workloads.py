@@ -155,5 +155,27 @@ def run_serve(args):
                              "overlapped_admissions": srv.overlapped_admissions, **st}
         _log("serve at %.2f x capacity: p50 %.3f ms, p99 %.3f ms" % (frac, st["p50_ms"], st["p99_ms"]))
     out["poisson"] = levels
+    # the same stream with every 10th request an integer product of L 16-bit limbs
+    # (three-prime transform, CRT and carries), at 0.8 of the polynomial capacity
+    def make_mixed(arrivals):
+        reqs = make(arrivals)
+        for k in range(0, n, 10):
+            r = reqs[k]
+            L = r.a.size
+            a = inputs.limbs16(L, inputs.CFG_SERVE, r.rid, 0)
+            b = inputs.limbs16(L, inputs.CFG_SERVE, r.rid, 1)
+            reqs[k] = serve.Request(r.rid, 0, a, b, arrival=r.arrival, kind="int")
+        return reqs
+    warm = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    warm.run(make_mixed([0.0] * n), realtime=False)
+    arr = inputs.poisson_arrivals(n, 0.8 * capacity, 80)
+    srv = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    w = srv.run(make_mixed(arr), realtime=True)
+    st = serve.latency_stats(srv.completed)
+    ints = [r for r in srv.completed if r.kind == "int"]
+    out["with_integer_products"] = {"share": 0.1, "offered_rps": round(0.8 * capacity, 2), "achieved_rps": round(n / w, 2),
+                                    "integer_requests": len(ints), "integer_p50_p99_ms": [
+                                        serve.latency_stats(ints)["p50_ms"], serve.latency_stats(ints)["p99_ms"]], **st}
+    _log("serve with integer products: p50 %.3f ms, p99 %.3f ms" % (st["p50_ms"], st["p99_ms"]))
     torch.cuda.synchronize()
     return out

@@ -1,11 +1,13 @@
-"""Continuous-batching server for polynomial products mod p on one GPU.
+"""Continuous-batching server for polynomial and integer products on one GPU.
 
-Requests (p, a, b) arrive over time with their operands in host memory.  The
+Requests arrive over time with their operands in host memory: polynomial products
+(p, a, b) and integer products (16-bit limbs a, b; ``Request.kind == "int"``).  The
 scheduler admits a request when its device footprint (operands, product and
-workspace) fits in the HBM budget, groups the admitted requests into one batched
-launch (``polymul_modp_batch``: one fused launch per size class, several primes and
-lengths together), and issues copies and launch on one of several streams.  Requests
-that arrive while earlier batches run are admitted as soon as memory frees up, so
+workspace) fits in the HBM budget, groups the admitted polynomial requests into one
+batched launch (``polymul_modp_batch``: one fused launch per size class, several
+primes and lengths together), issues each admitted integer product as one
+``intmul_crt`` call, and spreads copies and launches over several streams.  Requests
+that arrive while earlier work runs are admitted as soon as memory frees up, so
 their work overlaps on the device.  Plans (twiddle tables) stay resident in the
 library's cache.  Latency = arrival -> product resident in device memory.
 
@@ -73,8 +75,8 @@ class Arena:
 @dataclass
 class Request:
     rid: int
-    p: int
-    a: np.ndarray          # host operands (uint32 or uint64 residues)
+    p: int                 # prime of a polynomial product (ignored for "int")
+    a: np.ndarray          # host operands: uint32/uint64 residues, or uint16 limbs
     b: np.ndarray
     arrival: float = 0.0   # seconds since the start of the run
     admitted: float = -1.0
@@ -82,6 +84,7 @@ class Request:
     result: Optional[object] = None  # device tensor (view into the arena) or host copy
     blocks: List = field(default_factory=list)
     bfly: int = 0
+    kind: str = "poly"     # "poly" (product mod p) or "int" (integer product)
 
 
 def footprint(p: int, la: int, lb: int) -> int:
@@ -94,10 +97,24 @@ def footprint(p: int, la: int, lb: int) -> int:
     return Arena.round(la * esz) + Arena.round(lb * esz) + Arena.round(lc * esz) + Arena.round(ws) + desc
 
 
-def butterflies(la: int, lb: int) -> int:
+def int_footprint(na: int, nb: int) -> int:
+    """Device bytes of an integer product in flight (limbs, product limbs, workspace)."""
+    L = ntt.load()
+    nc = (na + nb + 1) // 2
+    return (Arena.round(2 * na) + Arena.round(2 * nb) + Arena.round(4 * nc)
+            + Arena.round(L.intmul_workspace_bytes(na, nb)))
+
+
+def request_footprint(r: "Request") -> int:
+    if r.kind == "int":
+        return int_footprint(r.a.size, r.b.size)
+    return footprint(r.p, r.a.size, r.b.size)
+
+
+def butterflies(la: int, lb: int, primes: int = 1) -> int:
     lc = la + lb - 1
     log2n = max(0, (lc - 1).bit_length())
-    return 3 * ((1 << log2n) // 2) * log2n
+    return primes * 3 * ((1 << log2n) // 2) * log2n
 
 
 class Server:
@@ -118,11 +135,18 @@ class Server:
     # --------------------------------------------------------------- memory
     def _try_admit(self, r: Request) -> bool:
         torch = self.torch
-        esz = 4 if r.p < (1 << 31) else 8
-        dt = torch.int32 if esz == 4 else torch.int64
         la, lb = r.a.size, r.b.size
-        lc = la + lb - 1
-        sizes = [la * esz, lb * esz, lc * esz]
+        if r.kind == "int":
+            nc = (la + lb + 1) // 2
+            ws = ntt.load().intmul_workspace_bytes(la, lb)
+            sizes = [2 * la, 2 * lb, 4 * nc, max(ws, 1)]
+            dts = [torch.int16, torch.int16, torch.int32, torch.uint8]
+        else:
+            esz = 4 if r.p < (1 << 31) else 8
+            dt = torch.int32 if esz == 4 else torch.int64
+            lc = la + lb - 1
+            sizes = [la * esz, lb * esz, lc * esz]
+            dts = [dt, dt, dt]
         offs = []
         for n in sizes:
             o = self.arena.alloc(n)
@@ -132,7 +156,7 @@ class Server:
                 return False
             offs.append(o)
         r.blocks = list(zip(offs, sizes))
-        r.dev = [self.arena.view(o, n, dt) for o, n in zip(offs, sizes)]
+        r.dev = [self.arena.view(o, n, t) for o, n, t in zip(offs, sizes, dts)]
         return True
 
     def _release(self, r: Request):
@@ -143,8 +167,9 @@ class Server:
     # --------------------------------------------------------------- scheduling
     def submit(self, r: Request):
         torch = self.torch
-        r.bfly = butterflies(r.a.size, r.b.size)
-        view = np.int32 if r.a.dtype == np.uint32 else np.int64
+        r.bfly = butterflies(r.a.size, r.b.size, 3 if r.kind == "int" else 1)
+        view = {np.dtype(np.uint16): np.int16, np.dtype(np.uint32): np.int32,
+                np.dtype(np.uint64): np.int64}[np.dtype(r.a.dtype)]
         # page-locked host copies so the uploads are true asynchronous DMA
         r.ha = torch.from_numpy(np.ascontiguousarray(r.a).view(view)).pin_memory()
         r.hb = torch.from_numpy(np.ascontiguousarray(r.b).view(view)).pin_memory()
@@ -195,6 +220,25 @@ class Server:
             r.admitted = now
         return True
 
+    def _launch_int(self, r: Request, now: float):
+        torch = self.torch
+        L = ntt.load()
+        s = self.streams[self.next_stream % len(self.streams)]
+        self.next_stream += 1
+        a, b, c, ws = r.dev
+        with torch.cuda.stream(s):
+            a.copy_(r.ha, non_blocking=True)
+            b.copy_(r.hb, non_blocking=True)
+        ntt._check(L.intmul_crt(ntt._ptr(a), a.numel(), ntt._ptr(b), b.numel(), ntt._ptr(c), ntt._ptr(ws),
+                                ws.numel(), ntt._stream(s)), "intmul_crt")
+        ev = torch.cuda.Event()
+        ev.record(s)
+        if self.inflight:
+            self.overlapped_admissions += 1
+        self.inflight.append((ev, [r], None, s))
+        self.max_inflight_batches = max(self.max_inflight_batches, len(self.inflight))
+        r.admitted = now
+
     def _poll(self, now_fn):
         still = []
         for ev, group, ws, s in self.inflight:
@@ -205,6 +249,8 @@ class Server:
                     if self.keep_results:
                         # synchronous copy to the host before the arena block is reused
                         r.result = ntt.to_numpy(r.dev[2])
+                        if r.kind == "int":
+                            r.result = r.result.astype(np.uint32)
                     self._release(r)
                     r.dev = None
                     r.ha = r.hb = None
@@ -217,24 +263,27 @@ class Server:
 
     def _admit_and_launch(self, now: float):
         group, work = [], 0
+        launched = False
         while self.pending and len(group) < self.max_batch:
             r = self.pending[0]
             if not self._try_admit(r):
                 break
             self.pending.popleft()
+            if r.kind == "int":
+                self._launch_int(r, now)
+                launched = True
+                continue
             group.append(r)
             work += r.bfly
         if group:
-            if not self._launch(group, now):
-                return False
-            return True
-        return False
+            return self._launch(group, now) or launched
+        return launched
 
     def run(self, requests: List[Request], realtime: bool = True):
         """Serve `requests` (sorted by arrival); returns wall seconds of the run."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         for r in reqs:
-            fp = footprint(r.p, r.a.size, r.b.size)
+            fp = request_footprint(r)
             if fp > self.arena.budget:
                 raise ValueError("request %d needs %d bytes, more than the HBM budget %d" % (r.rid, fp, self.arena.budget))
         t0 = time.perf_counter()

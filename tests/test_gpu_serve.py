@@ -76,3 +76,28 @@ def test_serve_rejects_request_beyond_budget():
     srv = serve.Server(budget_bytes=4096)
     with pytest.raises(ValueError):
         srv.run(reqs)
+
+
+def test_serve_mixes_integer_and_polynomial_requests():
+    torch_cuda()
+    polys = _requests(30, rate=20000.0, lo=8.0, hi=14.0, seed=3)
+    g = np.random.default_rng(np.random.SeedSequence([14073383, 7, 3]))
+    ints = []
+    for k in range(12):
+        na = int(2 ** g.uniform(4, 15))
+        nb = int(2 ** g.uniform(4, 15))
+        a = inputs.limbs16(na, inputs.CFG_SERVE, 5000 + k, 0)
+        b = inputs.limbs16(nb, inputs.CFG_SERVE, 5000 + k, 1)
+        ints.append(serve.Request(90000 + k, 0, a, b, arrival=float(polys[2 * k].arrival), kind="int"))
+    reqs = polys + ints
+    say("serve mix of %d polynomial and %d integer products" % (len(polys), len(ints)))
+    srv = serve.Server(budget_bytes=256 << 20, streams=4, max_batch=16)
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    for r in ints:
+        alone = ntt.to_numpy(ntt.intmul(ntt.to_device(r.a), ntt.to_device(r.b)))
+        assert_equal_u(r.result, alone, "integer request %d mix vs alone" % r.rid)
+        assert_equal_u(r.result, oracle.intmul_pyint(r.a, r.b), "integer request %d vs Python int" % r.rid)
+    for r in polys:
+        assert_equal_u(r.result, _alone(r), "request %d mix vs alone" % r.rid)
+    assert srv.arena.used == 0
