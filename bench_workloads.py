@@ -51,15 +51,32 @@ def run(name, args):
         p, a, b = inputs.polymul_8k_inputs()
         da, db = ntt.to_device(a), ntt.to_device(b)
         dc = torch.empty(8191, dtype=torch.int32, device="cuda")
-        bt = ntt.Batch([(da, db)], [p], [dc])
+        L = ntt.load()
+        ws = torch.empty(max(L.polymul_workspace_bytes(p, 4096, 4096), 1), dtype=torch.uint8, device="cuda")
+        split = ntt.tune_get("single.split.w32.L13") or 0
+
+        def step():
+            ntt._check(L.polymul_modp(p, ntt._ptr(da), 4096, ntt._ptr(db), 4096, ntt._ptr(dc), ntt._ptr(ws),
+                                      ws.numel(), ntt._stream(stream)), "polymul_modp")
         steps = max(args.steps, 200)
-        ms, kms = _time(lambda: bt(stream), stream, steps, 20)
+        ms, kms = _time(step, stream, steps, 20)
+        # device time per product without the host's call overhead: 100 calls in one graph
+        g = ntt.Graph(stream)
+        with g:
+            for _ in range(100):
+                step()
+        gms, gkms = _time(lambda: g.replay(stream), stream, 20, 3)
+        g.close()
         bfly = 3 * 4096 * 13
-        _log("polymul8k: %.2f us/product (events %.2f us)" % (ms * 1e3, kms * 1e3))
+        _log("polymul8k: %.2f us/product per call (events %.2f us), %.2f us/product in a graph"
+             % (ms * 1e3, kms * 1e3, gkms * 10))
+        path = ("%d workgroups at once, then a recombination kernel" % (1 << split) if split
+                else "one workgroup")
         return _line("single polymul mod p latency (Gbutterflies/s)", bfly / (ms * 1e-3) / 1e9, "Gbfly/s", ms, steps, 20,
                      {"workload": "one product mod 998244353 of two length-4096 operands, transform length 8192"},
-                     {"us_per_product": round(ms * 1e3, 2), "kernel_us": round(kms * 1e3, 2),
-                      "note": "one workgroup on one CU: latency-bound"})
+                     {"us_per_product": round(ms * 1e3, 2), "events_us_per_call": round(kms * 1e3, 2),
+                      "graph_us_per_product": round(gkms * 10, 2),
+                      "path": path, "how": "polymul_modp calls on one stream; graph: 100 recorded calls per replay"})
     if name == "ntt2_24":
         p, x = inputs.ntt_2_24_inputs()
         plan = ntt.Plan(p, 24, 3, ntt.NTT_BITREV_OUT | ntt.NTT_BITREV_IN)

@@ -186,6 +186,11 @@ int polymul_batch_destroy(ntt_batch* batch);
  *                     14, 15 or 16 (default 16); above it the two-pass path (batches
  *                     keep the fused kernel up to 2^16)
  *   "fused.single.max.w64"  the same for 64-bit primes: 13, 14 or 15 (default 15)
+ *   "single.split.w32.L<L>" (11 <= L <= 16), "single.split.w64.L<L>" (11 <= L <= 15)
+ *                     a single product of length 2^L runs its 2^d sub-problems of
+ *                     2^(L-d) points on 2^d workgroups at once, then recombines them
+ *                     (latency path; workspace N words): d = 1, 2 or 3 with
+ *                     10 <= L - d <= 13 (32-bit) / 12 (64-bit), or 0 (default: off)
  * A choice applies to plans created afterwards: clear the plan cache to re-plan.
  * Every choice computes the same (unique, canonical) results.
  * ntt_tune_set / ntt_tune_get: NTT_EINVAL for an unknown key, a value out of range

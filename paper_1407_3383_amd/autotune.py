@@ -10,6 +10,8 @@ The choices (keys of ``ntt_tune_set``, see include/ntt_mi355x.h):
   the fused twist / forward x2 / entry-wise product / inverse kernel).
 * ``fused.single.max.w<W>``: up to which transform length a single product runs in
   the one-workgroup fused kernel rather than the two-pass path (many workgroups).
+* ``single.split.w<W>.L<L>``: whether a single product of length 2^L runs its 2^d
+  sub-problems on 2^d workgroups at once (the latency path), and with which d.
 
 Every candidate is timed with HIP events on its own stream, and every candidate's
 output is compared with the first candidate's (they must be identical: the results
@@ -36,6 +38,7 @@ SPLITS = {32: (14, 13, 12), 64: (13, 12)}
 TRANSFORM_L = {32: range(15, 25), 64: range(14, 22)}
 PRODUCT_L = {32: range(15, 24), 64: range(14, 22)}
 FUSED_L = {32: (15, 16), 64: (14, 15)}
+SPLIT_L = {32: range(11, 17), 64: range(11, 16)}
 SEED_ITEM = 4242
 
 
@@ -139,6 +142,27 @@ def tune_single_fused(wb: int, reps: int, stream):
     return key, best, times
 
 
+def tune_single_split(wb: int, L: int, reps: int, stream):
+    """Depth d of the split latency path for one product of length 2^L (0: not split)."""
+    import torch
+    p = PRODUCT_PRIMES[wb]
+    n = 1 << (L - 1)
+    a = ntt.to_device(inputs.residues(p, n, inputs.CFG_TEST, SEED_ITEM + 200 + L, 0))
+    b = ntt.to_device(inputs.residues(p, n, inputs.CFG_TEST, SEED_ITEM + 200 + L, 1))
+    c = torch.empty(2 * n - 1, dtype=a.dtype, device="cuda")
+    key = "single.split.w%d.L%d" % (wb, L)
+    times, outs = {}, []
+    for d in (0, 1, 2, 3):
+        if d and not 10 <= L - d <= (13 if wb == 32 else 12):
+            continue
+        ntt.tune_set(key, d)
+        ws = torch.empty(max(ntt.load().polymul_workspace_bytes(p, n, n), 1), dtype=torch.uint8, device="cuda")
+        times[d] = _time(lambda: ntt.polymul(a, b, p, out=c, stream=stream, workspace=ws), stream, reps)
+        outs.append(ntt.to_numpy(c))
+    _same(outs, key)
+    return key, min(times, key=times.get), times
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=ntt.TUNE_FILE)
@@ -161,17 +185,21 @@ def main(argv=None) -> int:
     for wb in (32, 64):
         Ls = list(TRANSFORM_L[wb])
         Ps = list(PRODUCT_L[wb])
+        Ss = list(SPLIT_L[wb])
         if args.quick:
-            Ls, Ps = Ls[:1] + Ls[-1:], Ps[:1]
-        # the single-product threshold first: it decides which product sizes take the
-        # two-pass path whose row length is tuned next
-        jobs += [("t", wb, L) for L in Ls] + [("f", wb, 0)] + [("p", wb, L) for L in Ps]
+            Ls, Ps, Ss = Ls[:1] + Ls[-1:], Ps[:1], Ss[2:3]
+        # the single-product threshold and split depths first: they decide which
+        # product sizes take the two-pass path whose row length is tuned next
+        jobs += ([("t", wb, L) for L in Ls] + [("f", wb, 0)] + [("s", wb, L) for L in Ss]
+                 + [("p", wb, L) for L in Ps])
     with torch.cuda.stream(stream):
         for kind, wb, L in jobs:
             if kind == "t":
                 key, best, times = tune_transform(wb, L, args.reps, stream)
             elif kind == "p":
                 key, best, times = tune_product(wb, L, args.reps, stream)
+            elif kind == "s":
+                key, best, times = tune_single_split(wb, L, args.reps, stream)
             else:
                 key, best, times = tune_single_fused(wb, args.reps, stream)
             ntt.tune_set(key, best)

@@ -55,6 +55,8 @@ bool capturing(hipStream_t s) {
 //   psplit.w<W>.L<L>  the same for the plans the products use
 //   fused.single.max.w<W>  largest log2 N of a single product served by the fused
 //                     one-workgroup kernel
+//   single.split.w<W>.L<L>  split depth d of a single product of length 2^L over 2^d
+//                     workgroups (0: not split)
 std::mutex g_tune_mu;
 std::map<std::string, int64_t> g_tune;
 
@@ -68,6 +70,11 @@ bool tune_valid(const std::string& key, int64_t v) {
     if (w == 32) return L >= 15 && L <= 26 && v >= 12 && v <= 14;
     if (w == 64) return L >= 14 && L <= 26 && v >= 12 && v <= 13;
     return false;
+  }
+  if (sscanf(key.c_str(), "single.split.w%d.L%d%c", &w, &L, &tail) == 2) {
+    if (w != 32 && w != 64) return false;
+    if (L < 11 || L > fused_max_log2n(w)) return false;
+    return v == 0 || split_supported(w, L, (int)v);
   }
   if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
     if (w == 32) return v >= 14 && v <= 16;
@@ -748,16 +755,25 @@ namespace {
 
 struct ProductShape {
   uint64_t p;
-  int wb;       // word bits
-  int L;        // log2 of the transform length
-  bool fused;   // one workgroup per product
+  int wb;         // word bits
+  int L;          // log2 of the transform length
+  bool fused;     // one workgroup per product
   size_t lc;
+  int split = 0;  // single products: 2^split workgroups (latency path), 0 = not split
 };
 
 // Largest log2 N for which a single product (polymul_modp, each prime of intmul_crt)
 // takes the fused one-workgroup kernel; above it the two-pass path.  Batches always
 // take the fused kernel up to its limit.
 int fused_limit(int wb) { return (int)tune_value(tune_key("fused.single.max", wb, -1), fused_max_log2n(wb)); }
+
+// Path of a single product: the split latency path when a split depth is chosen for
+// its size, else the fused kernel up to fused_limit, else the two-pass path.
+void single_path(ProductShape* s) {
+  s->split = (int)tune_value(tune_key("single.split", s->wb, s->L), 0);
+  if (s->split && !split_supported(s->wb, s->L, s->split)) s->split = 0;
+  s->fused = !s->split && s->L <= fused_limit(s->wb);
+}
 
 int shape_of(uint64_t p, size_t la, size_t lb, ProductShape* s) {
   int l = 0;
@@ -790,6 +806,7 @@ size_t fused_launch_ws(int wb, int cls, size_t count, int cus) {
 }
 
 size_t single_product_ws(const ProductShape& s, int cus) {
+  if (s.split) return align256(((size_t)1 << s.L) * (s.wb / 8));  // the 2^split partials
   return s.fused ? fused_launch_ws(s.wb, fused_class(s.wb, s.L), 1, cus) : multipass_product_ws(s);
 }
 
@@ -880,7 +897,7 @@ size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
   if (la == 0 || lb == 0) return 0;
   ProductShape s;
   if (shape_of(p, la, lb, &s)) return 0;
-  s.fused = s.L <= fused_limit(s.wb);
+  single_path(&s);
   return single_product_ws(s, current_cus());
 }
 
@@ -893,7 +910,7 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     ProductShape s;
     int rc = shape_of(p, la, lb, &s);
     if (rc) return rc;
-    s.fused = s.L <= fused_limit(s.wb);
+    single_path(&s);
     const size_t esz = s.wb / 8;
     if (!aligned_to(a, esz) || !aligned_to(b, esz) || !aligned_to(c, esz))
       return fail(NTT_EINVAL, "operands must be %zu-byte aligned", esz);
@@ -903,6 +920,21 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     ntt_plan* pl = nullptr;
     rc = cached_plan(p, (uint32_t)s.L, &pl);
     if (rc) return rc;
+    if (s.split) {
+      SplitArgs x;
+      memset(&x, 0, sizeof(x));
+      x.a = a;
+      x.b = b;
+      x.c = c;
+      x.la = la;
+      x.lb = lb;
+      x.cst = pl->polyc;
+      x.tw = pl->tw;
+      x.twi = pl->twi;
+      x.park = workspace;
+      HIP_TRY(launch_split(s.wb, x, s.L, s.split, stream));
+      return ok();
+    }
     if (s.fused) {
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));

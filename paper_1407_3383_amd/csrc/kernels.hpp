@@ -86,6 +86,20 @@ hipError_t launch_range_check(int word_bits, const void* x, uint64_t n, uint64_t
 // attribute call.
 hipError_t allow_dynamic_lds(const void* kernel, size_t bytes);
 
+// One product on 2^d workgroups (latency path); park holds the 2^d partials (N words).
+struct SplitArgs {
+  const void* a;
+  const void* b;
+  void* c;
+  uint64_t la, lb;
+  const void* cst;  // PolyConst<T> of the plan
+  const void* tw;
+  const void* twi;
+  void* park;
+};
+bool split_supported(int word_bits, int log2n, int d);
+hipError_t launch_split(int word_bits, const SplitArgs& a, int log2n, int d, hipStream_t stream);
+
 struct CrtArgs {
   const uint32_t* r1;
   const uint32_t* r2;

@@ -85,6 +85,24 @@ def test_single_product_fused_threshold(fresh, p, n, limits):
         assert_equal_u(ntt.to_numpy(ntt.polymul(da, db, p)), want, "fused limit 2^%d" % lim)
 
 
+@pytest.mark.parametrize("p,la,lb,L", [(998244353, 4096, 4096, 13), (998244353, 3000, 77, 12),
+                                       (2013265921, 1 << 15, 1 << 15, 16), (2013265921, 1, 2047, 11),
+                                       (469762049, 5000, 9000, 14), (4611685941117976577, 2048, 2048, 12),
+                                       (4611685941117976577, 10000, 6000, 14)])
+def test_single_product_split_paths(fresh, p, la, lb, L):
+    a = inputs.residues(p, la, inputs.CFG_TEST, 1500 + L, 0)
+    b = inputs.residues(p, lb, inputs.CFG_TEST, 1500 + L, 1)
+    want = oracle.polymul_ntt(a, b, p, numtheory.smallest_generator(p))
+    da, db = ntt.to_device(a), ntt.to_device(b)
+    w = ntt.word_bits(p)
+    for d in (1, 2, 3):
+        if not 10 <= L - d <= (13 if w == 32 else 12):
+            continue
+        ntt.tune_set("single.split.w%d.L%d" % (w, L), d)
+        say("split product p=%d la=%d lb=%d over 2^%d workgroups" % (p, la, lb, d))
+        assert_equal_u(ntt.to_numpy(ntt.polymul(da, db, p)), want, "split depth %d" % d)
+
+
 def test_intmul_under_fused_threshold_choices(fresh):
     a = inputs.limbs16(20000, inputs.CFG_TEST, 1400, 0)
     b = inputs.limbs16(12000, inputs.CFG_TEST, 1400, 1)

@@ -23,7 +23,9 @@ def lib():
 @pytest.mark.parametrize("key,value", [
     ("split.w32.L24", 12), ("split.w32.L15", 14), ("split.w32.L26", 13), ("split.w64.L14", 12),
     ("split.w64.L21", 13), ("psplit.w32.L22", 12), ("psplit.w64.L20", 13),
-    ("fused.single.max.w32", 14), ("fused.single.max.w32", 16), ("fused.single.max.w64", 13)])
+    ("fused.single.max.w32", 14), ("fused.single.max.w32", 16), ("fused.single.max.w64", 13),
+    ("single.split.w32.L13", 3), ("single.split.w32.L16", 3), ("single.split.w32.L11", 1), ("single.split.w32.L14", 0),
+    ("single.split.w64.L15", 3), ("single.split.w64.L12", 2)])
 def test_valid_choices_round_trip(lib, key, value):
     ntt.tune_set(key, value)
     assert ntt.tune_get(key) == value
@@ -32,7 +34,9 @@ def test_valid_choices_round_trip(lib, key, value):
 @pytest.mark.parametrize("key,value", [
     ("split.w32.L24", 11), ("split.w32.L24", 15), ("split.w64.L20", 14), ("split.w32.L14", 12),
     ("split.w32.L27", 14), ("split.w16.L20", 12), ("split.w32.L20x", 12), ("fused.single.max.w32", 17),
-    ("fused.single.max.w64", 16), ("fused.max.w32", 15), ("", 1), ("row.w32.L20", 12)])
+    ("fused.single.max.w64", 16), ("fused.max.w32", 15), ("", 1), ("row.w32.L20", 12),
+    ("single.split.w32.L16", 2), ("single.split.w32.L12", 3), ("single.split.w32.L17", 3), ("single.split.w32.L10", 0),
+    ("single.split.w64.L15", 2), ("single.split.w32.L14", 4)])
 def test_invalid_choices_are_refused(lib, key, value):
     with pytest.raises(ntt.NTTError):
         ntt.tune_set(key, value)
