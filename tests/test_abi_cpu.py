@@ -105,7 +105,15 @@ def test_intmul_argument_errors(lib):
 
 
 def test_workspace_sizes(lib):
-    assert lib.polymul_workspace_bytes(998244353, 4096, 4096) == 0          # fused, no scratch
+    ntt.tune_clear()  # built-in defaults: the 8192-point product is fused in one workgroup
+    try:
+        assert lib.polymul_workspace_bytes(998244353, 4096, 4096) == 0      # fused, no scratch
+        ntt.tune_set("single.split.w32.L13", 1)                              # split: the 2 partials
+        assert lib.polymul_workspace_bytes(998244353, 4096, 4096) == 4 * 8192
+    finally:
+        ntt.tune_clear()
+        if os.path.exists(ntt.TUNE_FILE):
+            ntt.tune_load(ntt.TUNE_FILE)
     assert lib.polymul_workspace_bytes(998244353, 1 << 20, 1 << 20) >= 2 * 4 * (1 << 21)
     assert lib.polymul_workspace_bytes(998244353, 0, 5) == 0
     assert lib.intmul_workspace_bytes(1 << 21, 1 << 21) >= 3 * 4 * ((1 << 22) - 1)
