@@ -66,9 +66,24 @@ struct Arith<uint32_t> {
   // Function 8 (fixed multiplicand y = w, psi = ws) with the final correction left
   // out: for ANY x < 2^32 the result x w - floor(x ws / 2^32) p lies in [0, 2p)
   // (Proposition 4's bound with x not reduced), computed modulo 2^32 since 2p < 2^32.
+  // The low word x w + q (2^32 - p) comes from two v_mad_u64_u32 (x w, then + q (2^32
+  // - p)): three instructions with the v_mul_hi_u32, one fewer than mul_lo, mul_lo
+  // and a subtraction.  Only the low words are used; the carry-out goes to vcc.
   __device__ __forceinline__ uint32_t shoup(uint32_t x, uint32_t w, uint32_t ws) const {
-    uint32_t q = __umulhi(x, ws);
-    return x * w - q * p;
+    const uint32_t q = __umulhi(x, ws);
+    uint64_t d1, d2;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(d1) : "v"(x), "v"(w) : "vcc");
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(d2) : "v"(q), "s"(0u - p), "v"(d1) : "vcc");
+    return (uint32_t)d2;
+  }
+  // The same for a multiplicand that is the same in every lane of the wave (held in
+  // a scalar register; callers pass only values that went through uni()).
+  __device__ __forceinline__ uint32_t shoup_u(uint32_t x, uint32_t w, uint32_t ws) const {
+    const uint32_t q = __umulhi(x, ws);
+    uint64_t d1, d2;
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, 0" : "=v"(d1) : "v"(x), "s"(w) : "vcc");
+    asm("v_mad_u64_u32 %0, vcc, %1, %2, %3" : "=v"(d2) : "v"(q), "s"(0u - p), "v"(d1) : "vcc");
+    return (uint32_t)d2;
   }
   // Function 2's min trick: [0, 2p) -> [0, p) and [0, 4p) -> [0, 2p).
   __device__ __forceinline__ uint32_t red1(uint32_t x) const { return min(x, x - p); }
@@ -91,6 +106,7 @@ struct Arith<uint64_t> {
     uint64_t q = __umul64hi(x, ws);
     return x * w - q * p;
   }
+  __device__ __forceinline__ uint64_t shoup_u(uint64_t x, uint64_t w, uint64_t ws) const { return shoup(x, w, ws); }
   __device__ __forceinline__ uint64_t red1(uint64_t x) const {
     uint64_t y = x - p;
     return x < p ? x : y;
@@ -114,9 +130,10 @@ struct Arith<uint64_t> {
 // Forward, Cooley-Tukey form (X, Y) -> (X + w Y, X - w Y):
 //   LAZY: X in [0,4p), Y < 2^bits  ->  both outputs in [0,4p)
 //   SAFE: X in [0,2p), Y < 2^bits  ->  both outputs in [0,2p)
-template <bool LAZY, typename T>
+// UNI: the twiddle is the same in every lane (it went through uni()).
+template <bool LAZY, bool UNI = false, typename T>
 __device__ __forceinline__ void ct_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
-  T t = ar.shoup(Y, tw.w, tw.ws);
+  T t = UNI ? ar.shoup_u(Y, tw.w, tw.ws) : ar.shoup(Y, tw.w, tw.ws);
   if constexpr (LAZY) {
     T x = ar.red2(X);
     X = x + t;
@@ -132,15 +149,17 @@ __device__ __forceinline__ void ct_bfly(const Arith<T>& ar, T& X, T& Y, const Tw
 // Inverse, Gentleman-Sande form (X, Y) -> (X + Y, (X - Y) w):
 //   LAZY: inputs in [0,2p) -> outputs in [0,2p)
 //   SAFE: inputs in [0,p)  -> outputs in [0,p)
-template <bool LAZY, typename T>
+template <bool LAZY, bool UNI = false, typename T>
 __device__ __forceinline__ void gs_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
   if constexpr (LAZY) {
     T s = ar.red2(X + Y);
-    Y = ar.shoup(X - Y + ar.p2, tw.w, tw.ws);
+    const T d = X - Y + ar.p2;
+    Y = UNI ? ar.shoup_u(d, tw.w, tw.ws) : ar.shoup(d, tw.w, tw.ws);
     X = s;
   } else {
     T s = ar.red1(X + Y);
-    Y = ar.red1(ar.shoup(X - Y + ar.p, tw.w, tw.ws));
+    const T d = X - Y + ar.p;
+    Y = ar.red1(UNI ? ar.shoup_u(d, tw.w, tw.ws) : ar.shoup(d, tw.w, tw.ws));
     X = s;
   }
 }

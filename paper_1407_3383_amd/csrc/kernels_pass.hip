@@ -156,7 +156,7 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
       const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
       const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
       T x = gi < A.valid ? (T)in[gi] : (T)0;
-      if (scale) x = ar.red1(ar.shoup(x, sig.w, sig.ws));
+      if (scale) x = ar.red1(ar.shoup_u(x, sig.w, sig.ws));
       s[cc * VS + lidx(r)] = x;
     }
   } else {
@@ -258,8 +258,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
         const TwPair<T> V = thread_factor(ar, (uint32_t)q * Rr, B, lo, hi, rcp32);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
-          v[0][cc] = ar.shoup(ar.shoup(v[0][cc], V.w, V.ws), D[cc].w, D[cc].ws);
-          if constexpr (KIND == 2) v[1][cc] = ar.shoup(ar.shoup(v[1][cc], V.w, V.ws), D[cc].w, D[cc].ws);
+          v[0][cc] = ar.shoup_u(ar.shoup(v[0][cc], V.w, V.ws), D[cc].w, D[cc].ws);
+          if constexpr (KIND == 2) v[1][cc] = ar.shoup_u(ar.shoup(v[1][cc], V.w, V.ws), D[cc].w, D[cc].ws);
         }
       } else {
 #pragma unroll
@@ -269,7 +269,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
           if constexpr (KIND == 2) v[1][cc] = twist2(ar, v[1][cc], e, B, lo, hi);
         }
       }
-      if constexpr (R > 0) cluster_fwd<T, LAZY, R, NV>(ar, v, 0, wf);
+      if constexpr (R > 0) cluster_fwd<T, LAZY, R, NV, true>(ar, v, 0, wf);
       const int lb0 = lidx(q);
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) {
@@ -342,12 +342,12 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
       T v[C];
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
-      if constexpr (R > 0) cluster_inv<T, LAZY, R>(ar, v, wi);
+      if constexpr (R > 0) cluster_inv<T, LAZY, R, true>(ar, v, wi);
       if constexpr (sizeof(T) == 4) {
         const TwPair<T> V = thread_factor(ar, (uint32_t)q * Rr, B, ilo, ihi, rcp32);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
-          T y = ar.shoup(ar.shoup(v[cc], V.w, V.ws), Di[cc].w, Di[cc].ws);
+          T y = ar.shoup_u(ar.shoup(v[cc], V.w, V.ws), Di[cc].w, Di[cc].ws);
           if constexpr (!LAZY) y = ar.red1(y);
           out[q + 1024 * cc] = y;
         }

@@ -168,6 +168,8 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
           q2[k] = (MAXD > 1) ? P2[k] : (T)0;
         }
       }
+      // recombination twiddles, loaded before any output store
+      const TwPair<T> w1 = uni(ldtw<T>(twi + 1)), w2 = uni(ldtw<T>(twi + 2)), w3 = uni(ldtw<T>(twi + 3));
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int j = tr + k * NT;
@@ -179,18 +181,17 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
           } else if (d == 1) {
             if constexpr (MAXD > 0) {
               T x = q0[k];
-              gs_bfly<LAZY>(ar, x, v0, ldtw<T>(twi + 1));
+              gs_bfly<LAZY, true>(ar, x, v0, w1);
               if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, x);
               if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, v0);
             }
           } else {
             if constexpr (MAXD > 1) {
               T x0 = q0[k], x1 = q1[k], x2 = q2[k], x3 = v0;
-              const TwPair<T> w1 = ldtw<T>(twi + 1), w2 = ldtw<T>(twi + 2), w3 = ldtw<T>(twi + 3);
-              gs_bfly<LAZY>(ar, x0, x1, w2);
-              gs_bfly<LAZY>(ar, x2, x3, w3);
-              gs_bfly<LAZY>(ar, x0, x2, w1);
-              gs_bfly<LAZY>(ar, x1, x3, w1);
+              gs_bfly<LAZY, true>(ar, x0, x1, w2);
+              gs_bfly<LAZY, true>(ar, x2, x3, w3);
+              gs_bfly<LAZY, true>(ar, x0, x2, w1);
+              gs_bfly<LAZY, true>(ar, x1, x3, w1);
               if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, x0);
               if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, x1);
               if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, x2);
@@ -264,27 +265,34 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       T v[C];
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
-      if constexpr (R > 0) cluster_inv<T, LAZY, R>(ar, v, wi);
+      if constexpr (R > 0) cluster_inv<T, LAZY, R, true>(ar, v, wi);
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) sink(i * C + cc, q + 1024 * cc, v[cc]);
     }
   };
 
-  for (int h = 0; h < nsub; ++h) {
-    const int t0 = opaque_tid();
-    // ---- boundary phase: fold inputs in flight, G' of h-1 and park, fold + G of h
-    T x0[EPT], x1[EPT], y0[EPT], y1[EPT];
+  // Fold inputs: the same positions of a and b for every sub-problem.  They are
+  // requested for sub-problem h + 1 at the end of the wave phase of h, when the wave
+  // phase's registers are free, so that the loads are in flight across the barrier.
+  T x0[EPT], x1[EPT], y0[EPT], y1[EPT];
+  auto request_fold_inputs = [&]() {
+    const int tq = opaque_tid();
 #pragma unroll
     for (int i = 0; i < CPT; ++i)
 #pragma unroll
       for (int cc = 0; cc < C; ++cc) {
         const int e = i * C + cc;
-        const uint64_t j = (uint64_t)(t0 + i * NT) + 1024u * cc;
+        const uint64_t j = (uint64_t)(tq + i * NT) + 1024u * cc;
         x0[e] = j < la ? a[j] : (T)0;
         y0[e] = j < lb ? b[j] : (T)0;
         x1[e] = (nsub > 1 && j + S < la) ? a[j + S] : (T)0;
         y1[e] = (nsub > 1 && j + S < lb) ? b[j + S] : (T)0;
       }
+  };
+  request_fold_inputs();
+  for (int h = 0; h < nsub; ++h) {
+    const int t0 = opaque_tid();
+    // ---- boundary phase: G' of h-1 and park, fold + G of h
     if constexpr (MAXD > 0) {
       if (h > 0) finish(h - 1, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
     }
@@ -300,10 +308,10 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         for (int cc = 0; cc < C; ++cc) {
           const int e = i * C + cc;
           T fa = x0[e];
-          T fb = ar.red1(ar.shoup(y0[e], fb0.w, fb0.ws));
+          T fb = ar.red1(ar.shoup_u(y0[e], fb0.w, fb0.ws));
           if (nsub > 1) {
-            fa = ar.red1(fa + ar.red1(ar.shoup(x1[e], fa1.w, fa1.ws)));
-            fb = ar.red1(fb + ar.red1(ar.shoup(y1[e], fb1.w, fb1.ws)));
+            fa = ar.red1(fa + ar.red1(ar.shoup_u(x1[e], fa1.w, fa1.ws)));
+            fb = ar.red1(fb + ar.red1(ar.shoup_u(y1[e], fb1.w, fb1.ws)));
           }
           if (more_terms) {
             const uint64_t j = (uint64_t)q + 1024u * cc;
@@ -322,7 +330,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
           v[0][cc] = fa;
           v[1][cc] = fb;
         }
-        if constexpr (R > 0) cluster_fwd<T, LAZY, R, 2>(ar, v, 0, wf);
+        if constexpr (R > 0) cluster_fwd<T, LAZY, R, 2, true>(ar, v, 0, wf);
         const int lb0 = lidx(q);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
@@ -351,6 +359,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       }
       inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
     }
+    if (h + 1 < nsub) request_fold_inputs();
     __syncthreads();
   }
   // ---- last boundary: G' of the last sub-problem and the recombination
@@ -369,6 +378,14 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
           q2[e] = d >= 2 ? park[2 * S + j] : (T)0;
         }
     }
+    // recombination twiddles, loaded before any output store (a load placed after a
+    // store would wait for the store as well)
+    TwPair<T> w1, w2, w3;
+    if constexpr (MAXD > 0) {
+      w1 = uni(ldtw<T>(twi + 1));
+      w2 = uni(ldtw<T>(twi + 2));
+      w3 = uni(ldtw<T>(twi + 3));
+    }
     finish(nsub - 1, t0, [&](int e, int j, T v) {
       const uint64_t jj = (uint64_t)j;
       if (d == 0) {
@@ -376,18 +393,17 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       } else if (d == 1) {
         if constexpr (MAXD > 0) {
           T u0 = q0[e], u1 = v;
-          gs_bfly<LAZY>(ar, u0, u1, ldtw<T>(twi + 1));
+          gs_bfly<LAZY, true>(ar, u0, u1, w1);
           if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
           if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
         }
       } else {
         if constexpr (MAXD > 1) {
           T u0 = q0[e], u1 = q1[e], u2 = q2[e], u3 = v;
-          const TwPair<T> w1 = uni(ldtw<T>(twi + 1)), w2 = uni(ldtw<T>(twi + 2)), w3 = uni(ldtw<T>(twi + 3));
-          gs_bfly<LAZY>(ar, u0, u1, w2);
-          gs_bfly<LAZY>(ar, u2, u3, w3);
-          gs_bfly<LAZY>(ar, u0, u2, w1);
-          gs_bfly<LAZY>(ar, u1, u3, w1);
+          gs_bfly<LAZY, true>(ar, u0, u1, w2);
+          gs_bfly<LAZY, true>(ar, u2, u3, w3);
+          gs_bfly<LAZY, true>(ar, u0, u2, w1);
+          gs_bfly<LAZY, true>(ar, u1, u3, w1);
           if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
           if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
           if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u2);

@@ -67,11 +67,11 @@ __device__ void split_sub(const SplitArgs& A, T* sa, T* sb, const Arith<T>& ar) 
       T sa_ = xa[f][0], sb_ = xb[f][0];
 #pragma unroll
       for (int k = 1; k < K; ++k) {
-        sa_ = ar.red1(sa_ + ar.red1(ar.shoup(xa[f][k], fa[k].w, fa[k].ws)));
-        sb_ = ar.red1(sb_ + ar.red1(ar.shoup(xb[f][k], fa[k].w, fa[k].ws)));
+        sa_ = ar.red1(sa_ + ar.red1(ar.shoup_u(xa[f][k], fa[k].w, fa[k].ws)));
+        sb_ = ar.red1(sb_ + ar.red1(ar.shoup_u(xb[f][k], fa[k].w, fa[k].ws)));
       }
       sa[lidx(j)] = sa_;
-      sb[lidx(j)] = ar.red1(ar.shoup(sb_, sigma.w, sigma.ws));  // b's fold times sigma
+      sb[lidx(j)] = ar.red1(ar.shoup_u(sb_, sigma.w, sigma.ws));  // b's fold times sigma
     }
   }
   __syncthreads();
@@ -133,7 +133,7 @@ __device__ __forceinline__ void recombine_one(const SplitArgs& A, const Arith<T>
     for (int blk = 0; blk < (1 << t); ++blk) {
       const TwPair<T> w = uni(ldtw<T>(twi + ((1 << t) + blk)));
 #pragma unroll
-      for (int i = 0; i < half; ++i) gs_bfly<LAZY>(ar, u[blk * 2 * half + i], u[blk * 2 * half + i + half], w);
+      for (int i = 0; i < half; ++i) gs_bfly<LAZY, true>(ar, u[blk * 2 * half + i], u[blk * 2 * half + i + half], w);
     }
   }
   const gptr<T> c = gmut<T>(A.c);

@@ -25,7 +25,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // Radix-2^R butterflies on a register cluster x[0 .. 2^R): cluster stage u pairs
 // (c, c + 2^(R-1-u)) with twiddle w[2^u - 1 + (c >> (R-u))].
-template <typename T, bool LAZY, int R, int NV>
+template <typename T, bool LAZY, int R, int NV, bool UNI = false>
 __device__ __forceinline__ void cluster_fwd(const Arith<T>& ar, T (&x)[NV][1 << R], int off, const TwPair<T>* w) {
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -37,14 +37,14 @@ __device__ __forceinline__ void cluster_fwd(const Arith<T>& ar, T (&x)[NV][1 << 
       for (int c2 = 0; c2 < half; ++c2) {
         const int c = (vv << (R - u)) + c2;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) ct_bfly<LAZY>(ar, x[v][c], x[v][c + half], ww);
+        for (int v = 0; v < NV; ++v) ct_bfly<LAZY, UNI>(ar, x[v][c], x[v][c + half], ww);
       }
     }
   }
   (void)off;
 }
 
-template <typename T, bool LAZY, int R>
+template <typename T, bool LAZY, int R, bool UNI = false>
 __device__ __forceinline__ void cluster_inv(const Arith<T>& ar, T* x, const TwPair<T>* w) {
 #pragma unroll
   for (int u = R - 1; u >= 0; --u) {
@@ -55,7 +55,7 @@ __device__ __forceinline__ void cluster_inv(const Arith<T>& ar, T* x, const TwPa
 #pragma unroll
       for (int c2 = 0; c2 < half; ++c2) {
         const int c = (vv << (R - u)) + c2;
-        gs_bfly<LAZY>(ar, x[c], x[c + half], ww);
+        gs_bfly<LAZY, UNI>(ar, x[c], x[c + half], ww);
       }
     }
   }
@@ -98,7 +98,7 @@ __device__ __forceinline__ void fwd_G(const Arith<T>& ar, T* const (&sv)[NV], in
       for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int c = 0; c < C; ++c) x[v][c] = sv[v][lb + c * 1056];  // lidx(q + 1024 c) = lidx(q) + 1056 c
-      cluster_fwd<T, LAZY, R, NV>(ar, x, 0, w);
+      cluster_fwd<T, LAZY, R, NV, true>(ar, x, 0, w);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -127,7 +127,7 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int c = 0; c < 16; ++c) x[v][c] = sv[v][lb + c * 66];  // lidx(base + lane + 64 c)
-    cluster_fwd<T, LAZY, 4, NV>(ar, x, 0, w);
+    cluster_fwd<T, LAZY, 4, NV, true>(ar, x, 0, w);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -215,7 +215,7 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
     const int lb = lbase + lane + (lane >> 5);
 #pragma unroll
     for (int c = 0; c < 16; ++c) x[c] = sa[lb + c * 66];
-    cluster_inv<T, LAZY, 4>(ar, x, w);
+    cluster_inv<T, LAZY, 4, true>(ar, x, w);
 #pragma unroll
     for (int c = 0; c < 16; ++c) sa[lb + c * 66] = x[c];
   }
@@ -237,7 +237,7 @@ __device__ __forceinline__ void inv_G(const Arith<T>& ar, T* sa, int d, uint32_t
       T x[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) x[c] = sa[lb + c * 1056];
-      cluster_inv<T, LAZY, R>(ar, x, w);
+      cluster_inv<T, LAZY, R, true>(ar, x, w);
 #pragma unroll
       for (int c = 0; c < C; ++c) sa[lb + c * 1056] = x[c];
     }
