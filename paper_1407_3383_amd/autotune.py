@@ -47,11 +47,14 @@ def _log(msg):
 
 
 def _time(fn, stream, reps: int) -> float:
-    """Mean milliseconds of fn() over `reps` calls, after two warm-up calls."""
+    """Mean milliseconds of fn() over `reps` calls, after warm-up calls (at least 50 ms
+    of them, so that the GPU clocks have ramped up)."""
     import torch
-    for _ in range(2):
-        fn()
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.05:
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
