@@ -48,6 +48,7 @@ def _line(metric, value, unit, ms, steps, warmup, config, extra):
 
 
 def run(name, args):
+    import numpy as np
     import torch
 
     from paper_1407_3383_amd import inputs, ntt
@@ -129,6 +130,30 @@ def run(name, args):
                       "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 2)},
                       "alu": {"achieved_Tops": round(bfly * OPS_PER_BFLY / (ms * 1e-3) / 1e12, 3),
                               "peak_Tops": round(ALU_PEAK_TOPS, 3)}})
+    if name == "intmul32":
+        # the same two integers as the integer-product configuration, in 32-bit chunks
+        # (section 5.3's choice of h for these primes): transform length 2^21
+        a, b = inputs.intmul_inputs()
+        a32 = np.ascontiguousarray(a).view("<u4").astype(np.uint32)
+        b32 = np.ascontiguousarray(b).view("<u4").astype(np.uint32)
+        da, db = ntt.to_device(a32), ntt.to_device(b32)
+        dc = torch.empty(a32.size + b32.size, dtype=torch.int32, device="cuda")
+        L = ntt.load()
+        ws = torch.empty(L.intmul32_workspace_bytes(a32.size, b32.size), dtype=torch.uint8, device="cuda")
+
+        def step():
+            ntt._check(L.intmul_crt32(ntt._ptr(da), a32.size, ntt._ptr(db), b32.size, ntt._ptr(dc), ntt._ptr(ws),
+                                      ws.numel(), ntt._stream(stream)), "intmul_crt32")
+        steps = max(args.steps, 10)
+        ms, kms = _time(step, stream, steps, 2)
+        N = 1 << 21
+        bfly = 3 * 3 * (N // 2) * 21
+        _log("intmul32: %.3f ms per product" % ms)
+        return _line("three-prime integer product 2^25 x 2^25 bits, 32-bit chunks (Gbutterflies/s)",
+                     bfly / (ms * 1e-3) / 1e9, "Gbfly/s", ms, steps, 2,
+                     {"workload": "product of the same two 2^25-bit integers as 2^20 chunks of 32 bits (h = 32 by "
+                                  "the chunk-size rule), primes 998244353, 469762049, 167772161, transform length 2^21"},
+                     {"ms_per_product": round(ms, 4), "chunk_bits": ntt.intmul_chunk_bits(a.size, b.size)})
     if name == "serve":
         return run_serve(args)
     raise ValueError(name)

@@ -241,6 +241,24 @@ size_t intmul_workspace_bytes(size_t na, size_t nb);
 int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint32_t* c, void* workspace,
                size_t ws_bytes, void* hip_stream);
 
+/* Section 5.3's choice of the chunk size h for integers of na16 and nb16 16-bit
+ * limbs: the largest h in {32, 16} with 2^(2h + ceil(log2(d + 1))) < p1 p2 p3 (d the
+ * larger chunk count) and d_a + d_b - 1 <= 2^23; 0 when neither fits. */
+int intmul_chunk_bits(size_t na16, size_t nb16);
+
+size_t intmul32_workspace_bytes(size_t na, size_t nb);
+
+/* c = a * b for nonnegative integers given as little-endian 32-bit chunks (h = 32:
+ * half the transform length of the 16-bit path for the same integers; a 16-bit-limb
+ * integer with an even limb count is the same array read as 32-bit chunks).  c
+ * receives exactly na + nb little-endian 32-bit limbs, unnormalised.  Each chunk is
+ * reduced modulo each prime first (2^32 exceeds them).  na == 0 or nb == 0 writes
+ * zeros.  Errors: NTT_EINVAL (NULL or misaligned pointers; min(na, nb) (2^32 - 1)^2
+ * reaching p1 p2 p3, about min(na, nb) > 4.26e6; na + nb - 1 > 2^23), NTT_ENOMEM
+ * (workspace), NTT_EDEVICE. */
+int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uint32_t* c, void* workspace,
+                 size_t ws_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

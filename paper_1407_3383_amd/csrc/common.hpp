@@ -43,6 +43,7 @@ struct PassConst {
   T p, p2, pinv, lazy;
   TwPair<T> ninv;     // n^-1
   TwPair<T> sigma;    // 2^bits(T) / N mod p
+  TwPair<T> one;      // (1, floor(2^bits(T) / p)): Function 8 by 1 reduces any word to [0, 2p)
   uint32_t L, L1, L2, B;
   double rcp32;       // 2^32 / p rounded: estimates Shoup companions of 32-bit residues
 };

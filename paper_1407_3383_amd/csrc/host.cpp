@@ -365,6 +365,7 @@ int build_plan_tables(ntt_plan* pl) {
   sc.lazy = (T)(pl->lazy ? 1 : 0);
   sc.ninv = pair_of<T>(pl->ninv, p);
   sc.sigma = pair_of<T>(sigma, p);
+  sc.one = pair_of<T>(1, p);
   sc.L = (uint32_t)L;
   sc.L1 = pl->L1;
   sc.L2 = pl->L2;
@@ -851,6 +852,68 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   x.out = c;
   x.valid = lc;
   HIP_TRY(launch_col_inv(wb, x, L1, L2, stream));
+  return NTT_OK;
+}
+
+// Two-pass products of the same operands modulo n primes of equal transform length
+// (several moduli in one launch, section 2.2's Remark 6): the 2n column passes, the n
+// fused row passes and the n inverse column passes each share one launch.  input: 0
+// canonical residues, 1 16-bit limbs, 2 32-bit words that may exceed the primes.
+// Workspace: n * 2 * N words.
+int run_multipass_products(ntt_plan* const* pls, int n, const void* a, size_t la, const void* b, size_t lb,
+                           void* const* c, size_t lc, int input, void* ws, hipStream_t stream) {
+  if (n < 1 || 2 * n > kMaxPassJobs) return fail(NTT_EINVAL, "too many primes in one launch");
+  const int wb = (int)pls[0]->wbits;
+  const size_t N = (size_t)1 << pls[0]->log2n;
+  const int L1 = (int)pls[0]->L1, L2 = (int)pls[0]->L2;
+  for (int i = 1; i < n; ++i)
+    if ((int)pls[i]->wbits != wb || pls[i]->L1 != (uint32_t)L1 || pls[i]->L2 != (uint32_t)L2)
+      return fail(NTT_EINVAL, "products of one launch need the same transform shape");
+  unsigned char* w = (unsigned char*)ws;
+  const size_t vec = align256(N * (wb / 8));
+  PassJobs fwd, row, inv;
+  memset(&fwd, 0, sizeof(fwd));
+  memset(&row, 0, sizeof(row));
+  memset(&inv, 0, sizeof(inv));
+  for (int i = 0; i < n; ++i) {
+    const ntt_plan* pl = pls[i];
+    void* A = w + (size_t)(2 * i) * vec;
+    void* B = w + (size_t)(2 * i + 1) * vec;
+    PassArgs x;
+    memset(&x, 0, sizeof(x));
+    x.pc = pl->passc;
+    x.tw = pl->tw;
+    x.twi = pl->twi;
+    x.tlo = pl->tlo;
+    x.thi = pl->thi;
+    x.tilo = pl->tilo;
+    x.tihi = pl->tihi;  // no n^-1: the Montgomery scale folded into b carries it
+    x.batch = 1;
+    x.in_u16 = input == 1 ? 1 : 0;
+    x.in = a;
+    x.out = A;
+    x.valid = la;
+    x.scale = input == 2 ? 2 : 0;
+    fwd.j[fwd.n++] = x;
+    x.in = b;
+    x.out = B;
+    x.valid = lb;
+    x.scale = 1;
+    fwd.j[fwd.n++] = x;
+    x.in_u16 = 0;
+    x.scale = 0;
+    x.in = A;
+    x.in2 = B;
+    x.out = A;
+    row.j[row.n++] = x;
+    x.in2 = nullptr;
+    x.out = c[i];
+    x.valid = lc;
+    inv.j[inv.n++] = x;
+  }
+  HIP_TRY(launch_col_fwd_jobs(wb, fwd, L1, L2, stream));
+  HIP_TRY(launch_row_polymul_jobs(wb, row, L1, L2, stream));
+  HIP_TRY(launch_col_inv_jobs(wb, inv, L1, L2, stream));
   return NTT_OK;
 }
 
@@ -1345,7 +1408,7 @@ IntLayout int_layout(size_t na, size_t nb) {
     off += fused_launch_ws(32, fused_class(32, z.L), 1, current_cus());
   } else {
     z.o_big = off;
-    off += 2 * align256(z.N * 4);
+    off += 3 * 2 * align256(z.N * 4);  // the three primes' products share their launches
   }
   z.total = off;
   return z;
@@ -1391,21 +1454,24 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
       a_in = a32;
       b_in = b32;
     }
+    ntt_plan* pls[3];
     for (int i = 0; i < 3; ++i) {
-      ntt_plan* pl = nullptr;
-      int rc = cached_plan(kIntPrimes[i], (uint32_t)z.L, &pl);
+      int rc = cached_plan(kIntPrimes[i], (uint32_t)z.L, &pls[i]);
       if (rc) return rc;
-      if (z.fused) {
+    }
+    if (z.fused) {
+      for (int i = 0; i < 3; ++i) {
         FusedBatch fb;
         memset(&fb, 0, sizeof(fb));
         fb.count = 1;
         fb.park = w + z.o_big;
-        fb.single = fused_item(pl, a_in, na, b_in, nb, r[i]);
+        fb.single = fused_item(pls[i], a_in, na, b_in, nb, r[i]);
         HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
-      } else {
-        rc = run_multipass_product(pl, a, na, b, nb, r[i], z.lc, true, w + z.o_big, stream);
-        if (rc) return rc;
       }
+    } else {
+      void* outs[3] = {r[0], r[1], r[2]};
+      int rc = run_multipass_products(pls, 3, a, na, b, nb, outs, z.lc, 1, w + z.o_big, stream);
+      if (rc) return rc;
     }
     CrtArgs x;
     memset(&x, 0, sizeof(x));
@@ -1438,3 +1504,156 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------- integer product, 32-bit chunks
+namespace {
+
+// p1 p2 p3 of the three primes (a bit over 2^86).
+u128 int_prime_product() { return (u128)kIntPrimes[0] * kIntPrimes[1] * kIntPrimes[2]; }
+
+struct Int32Layout {
+  size_t lc, npos, N, nblk;
+  int L;
+  bool fused;
+  size_t o_r[3], o_t, o_blk, o_a, o_b, o_big, total;
+};
+
+Int32Layout int32_layout(size_t na, size_t nb) {
+  Int32Layout z;
+  memset(&z, 0, sizeof(z));
+  z.lc = na + nb - 1;
+  z.L = ceil_log2(z.lc);
+  z.N = (size_t)1 << z.L;
+  z.npos = na + nb;
+  z.nblk = (z.npos + crt_block_positions() - 1) / crt_block_positions();
+  z.fused = z.L <= fused_limit(32);
+  size_t off = 0;
+  for (int i = 0; i < 3; ++i) {
+    z.o_r[i] = off;
+    off += align256(z.lc * 4);
+  }
+  z.o_t = off;
+  off += align256(z.nblk * crt_block_positions() * 8);
+  z.o_blk = off;
+  off += align256(z.nblk * 4);
+  z.o_a = off;
+  off += align256(na * 4);
+  z.o_b = off;
+  off += align256(nb * 4);
+  z.o_big = off;
+  off += z.fused ? fused_launch_ws(32, fused_class(32, z.L), 1, current_cus()) : 3 * 2 * align256(z.N * 4);
+  z.total = off;
+  return z;
+}
+
+// The product of two na- and nb-chunk integers has coefficients below
+// min(na, nb) (2^32 - 1)^2, which the three primes must exceed.
+bool int32_fits(size_t na, size_t nb) {
+  const u128 m = (u128)std::min(na, nb);
+  const u128 cmax = m * (u128)0xFFFFFFFFull * (u128)0xFFFFFFFFull;
+  return cmax < int_prime_product() && na + nb - 1 <= kIntMaxCoeffs;
+}
+
+}  // namespace
+
+extern "C" {
+
+int intmul_chunk_bits(size_t na16, size_t nb16) {
+  // Section 5.3: the largest chunk size h (here 32 or 16) such that
+  // H = 2 h + ceil(log2(d + 1)) bits, d the chunk count, stay below p1 p2 p3, and the
+  // product's d_a + d_b - 1 coefficients fit the primes' transform lengths.
+  if (na16 == 0 || nb16 == 0) return 16;
+  for (int h : {32, 16}) {
+    const size_t per = (size_t)h / 16;
+    const size_t da = (na16 + per - 1) / per, db = (nb16 + per - 1) / per;
+    const size_t d = std::max(da, db);
+    const int H = 2 * h + ceil_log2(d + 1);
+    if (H < 127 && ((u128)1 << H) < int_prime_product() && da + db - 1 <= kIntMaxCoeffs) return h;
+  }
+  return 0;
+}
+
+size_t intmul32_workspace_bytes(size_t na, size_t nb) {
+  if (na == 0 || nb == 0) return 0;
+  if (!int32_fits(na, nb)) return 0;
+  return int32_layout(na, nb).total;
+}
+
+int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uint32_t* c, void* workspace,
+                 size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    const size_t nc = na + nb;
+    if (nc && !c) return fail(NTT_EINVAL, "output pointer is NULL");
+    if (!aligned_to(c, 4) || !aligned_to(a, 4) || !aligned_to(b, 4)) return fail(NTT_EINVAL, "misaligned pointer");
+    if (na == 0 || nb == 0) {
+      HIP_TRY(launch_fill_u32(c, nc, 0u, stream));
+      return ok();
+    }
+    if (!a || !b) return fail(NTT_EINVAL, "NULL operand pointer");
+    if (!int32_fits(na, nb))
+      return fail(NTT_EINVAL, "%zu x %zu chunks of 32 bits: coefficients could reach p1 p2 p3 or exceed 2^23 of them",
+                  na, nb);
+    const Int32Layout z = int32_layout(na, nb);
+    if (ws_bytes < z.total || !workspace)
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", z.total, ws_bytes);
+    unsigned char* w = (unsigned char*)workspace;
+    uint32_t* r[3];
+    for (int i = 0; i < 3; ++i) r[i] = (uint32_t*)(w + z.o_r[i]);
+    uint32_t* ar = (uint32_t*)(w + z.o_a);
+    uint32_t* br = (uint32_t*)(w + z.o_b);
+    ntt_plan* pls[3];
+    for (int i = 0; i < 3; ++i) {
+      int rc = cached_plan(kIntPrimes[i], (uint32_t)z.L, &pls[i]);
+      if (rc) return rc;
+    }
+    if (z.fused) {
+      for (int i = 0; i < 3; ++i) {
+        // chunks of 32 bits exceed the primes: reduce them first
+        HIP_TRY(launch_reduce_mod(a, ar, na, kIntPrimes[i], stream));
+        HIP_TRY(launch_reduce_mod(b, br, nb, kIntPrimes[i], stream));
+        FusedBatch fb;
+        memset(&fb, 0, sizeof(fb));
+        fb.count = 1;
+        fb.park = w + z.o_big;
+        fb.single = fused_item(pls[i], ar, na, br, nb, r[i]);
+        HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
+      }
+    } else {
+      // the column pass reduces the chunks as it loads them (input kind 2)
+      void* outs[3] = {r[0], r[1], r[2]};
+      int rc = run_multipass_products(pls, 3, a, na, b, nb, outs, z.lc, 2, w + z.o_big, stream);
+      if (rc) return rc;
+    }
+    CrtArgs x;
+    memset(&x, 0, sizeof(x));
+    x.r1 = r[0];
+    x.r2 = r[1];
+    x.r3 = r[2];
+    x.lc = z.lc;
+    x.npos = z.npos;
+    x.t = (uint32_t*)(w + z.o_t);
+    x.blk = (uint32_t*)(w + z.o_blk);
+    x.c = c;
+    const uint64_t p1 = kIntPrimes[0], p2 = kIntPrimes[1], p3 = kIntPrimes[2];
+    x.p1 = (uint32_t)p1;
+    x.p2 = (uint32_t)p2;
+    x.p3 = (uint32_t)p3;
+    const uint64_t c12 = invmod(p1 % p2, p2);
+    const uint64_t c123 = invmod(mulmod(p1 % p3, p2 % p3, p3), p3);
+    x.c12 = (uint32_t)c12;
+    x.c12s = (uint32_t)((c12 << 32) / p2);
+    x.c123 = (uint32_t)c123;
+    x.c123s = (uint32_t)((c123 << 32) / p3);
+    x.p1m3 = (uint32_t)(p1 % p3);
+    x.p1m3s = (uint32_t)(((p1 % p3) << 32) / p3);
+    x.p1p2 = p1 * p2;
+    HIP_TRY(launch_crt32_carry(x, stream));
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in intmul_crt32");
+  }
+}
+
+}  // extern "C"
+

@@ -54,10 +54,21 @@ struct PassArgs {
   const void* tilo;
   const void* tihi;
   uint32_t batch;
-  uint32_t scale;   // column forward pass: multiply inputs by sigma (second operand of a product)
+  uint32_t scale;   // column forward pass: 1 multiply inputs by sigma (second operand of a product),
+                    // 2 reduce inputs modulo p (words that may exceed p), 0 neither
   uint32_t in_u16;  // column forward pass: input is 16-bit limbs
   uint32_t pad;
 };
+// Up to kMaxPassJobs passes of the same shape (word, L1, L2, batch, input type) whose
+// workgroups share one launch: job = blockIdx.y (several primes, both operands).
+constexpr int kMaxPassJobs = 6;
+struct PassJobs {
+  PassArgs j[kMaxPassJobs];
+  int n;
+};
+hipError_t launch_col_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_col_inv_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_row_polymul_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
@@ -117,5 +128,8 @@ struct CrtArgs {
 };
 int crt_block_positions();
 hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream);
+// 32-bit chunks: t holds whole blocks of 64-bit column sums, c gets npos 32-bit limbs.
+hipError_t launch_crt32_carry(const CrtArgs& a, hipStream_t stream);
+hipError_t launch_reduce_mod(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t p, hipStream_t stream);
 
 }  // namespace nttgpu

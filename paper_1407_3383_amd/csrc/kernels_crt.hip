@@ -187,4 +187,131 @@ hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ 32-bit chunks
+// The same tail for chunks of h = 32 bits (section 5.3's choice of h for these
+// primes): v_k < p1 p2 p3 < 2^87 takes three 32-bit digits, the column sum of
+// position m is s_m = d0(v_m) + d1(v_(m-1)) + d2(v_(m-2)) < 3 2^32, and
+// t_m = (s_m mod 2^32) + floor(s_(m-1) / 2^32) <= 2^32 + 1 leaves carries of 0 or 1
+// again, resolved by the same prefix maxima; the limbs are t_m + carry mod 2^32.
+constexpr int kCrt32Halo = 3;  // s_(m-1) reaches v_(m-3)
+
+namespace {
+
+// v = x1 + p1 x2 + p1 p2 x3 as (lo 64 bits, hi 32 bits).
+__device__ __forceinline__ void garner96(const CrtArgs& A, uint32_t r1, uint32_t r2, uint32_t r3, uint64_t& lo,
+                                         uint32_t& hi) {
+  const uint32_t x1 = r1;
+  const uint32_t x2 = red(shoup_lazy(r2 + 3u * A.p2 - x1, A.c12, A.c12s, A.p2), A.p2);
+  const uint32_t u = shoup_lazy(x2, A.p1m3, A.p1m3s, A.p3);
+  const uint32_t x3 = red(shoup_lazy(r3 + 8u * A.p3 - x1 - u, A.c123, A.c123s, A.p3), A.p3);
+  const uint64_t s = (uint64_t)x1 + (uint64_t)A.p1 * x2;  // < 2^60
+  const uint64_t bl = A.p1p2 * (uint64_t)x3;
+  const uint64_t bh = __umul64hi(A.p1p2, (uint64_t)x3);
+  lo = s + bl;
+  hi = (uint32_t)(bh + (lo < s ? 1u : 0u));
+}
+
+__device__ __forceinline__ uint32_t key32(uint64_t t, uint32_t j) {
+  return t == 0xFFFFFFFFull ? 0u : 2u * (j + 1u) + (t >= (1ull << 32) ? 1u : 0u);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kCrtNT) void crt32_phase1_kernel(CrtArgs A) {
+  __shared__ uint64_t vlo[kCrtBlock + kCrt32Halo];
+  __shared__ uint32_t vhi[kCrtBlock + kCrt32Halo];
+  __shared__ uint32_t wmax[kCrtNT / 64];
+  const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
+  gcptr<uint32_t> r1 = gconst<uint32_t>(A.r1);
+  gcptr<uint32_t> r2 = gconst<uint32_t>(A.r2);
+  gcptr<uint32_t> r3 = gconst<uint32_t>(A.r3);
+  for (int j = threadIdx.x; j < kCrtBlock + kCrt32Halo; j += kCrtNT) {
+    const int64_t k = (int64_t)mb - kCrt32Halo + j;
+    uint64_t lo = 0;
+    uint32_t hi = 0;
+    if (k >= 0 && (uint64_t)k < A.lc) garner96(A, r1[k], r2[k], r3[k], lo, hi);
+    vlo[j] = lo;
+    vhi[j] = hi;
+  }
+  __syncthreads();
+  uint32_t key = 0;
+  gptr<uint64_t> t = gmut<uint64_t>(A.t);
+#pragma unroll
+  for (int q = 0; q < kCrtPPT; ++q) {
+    const int lp = threadIdx.x + kCrtNT * q;  // position mb + lp: v_(m-i) at local lp + 3 - i
+    const uint64_t s = (vlo[lp + 3] & 0xFFFFFFFFull) + (vlo[lp + 2] >> 32) + (uint64_t)vhi[lp + 1];   // s_m
+    const uint64_t sp = (vlo[lp + 2] & 0xFFFFFFFFull) + (vlo[lp + 1] >> 32) + (uint64_t)vhi[lp];     // s_(m-1)
+    const uint64_t tm = (s & 0xFFFFFFFFull) + (sp >> 32);
+    t[mb + lp] = tm;
+    key = max(key, key32(tm, (uint32_t)lp));
+  }
+  key = wave_max(key);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t k = 0;
+#pragma unroll
+    for (int w = 0; w < kCrtNT / 64; ++w) k = max(k, wmax[w]);
+    gmut<uint32_t>(A.blk)[blockIdx.x] = k == 0 ? 2u : (k & 1u);
+  }
+}
+
+__global__ __launch_bounds__(kCrtNT) void crt32_phase3_kernel(CrtArgs A) {
+  __shared__ uint32_t wsum[kCrtNT / 64];
+  const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
+  const uint32_t lp0 = threadIdx.x * kCrtPPT;
+  const uint64_t* tv = (const uint64_t*)A.t + mb + lp0;  // the workspace holds whole blocks
+  uint64_t t[kCrtPPT];
+#pragma unroll
+  for (int q = 0; q < kCrtPPT; ++q) t[q] = tv[q];
+  uint32_t key = 0;
+#pragma unroll
+  for (int q = 0; q < kCrtPPT; ++q) key = max(key, key32(t[q], lp0 + q));
+  const uint32_t incl = wave_scan_max(key);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t below = 0;
+  for (int i = 0; i < w; ++i) below = max(below, wsum[i]);
+  const uint32_t up = (uint32_t)__shfl_up((int)incl, 1, 64);
+  const uint32_t excl = max(below, lane > 0 ? up : 0u);
+  uint64_t carry = excl == 0 ? gconst<uint32_t>(A.blk)[blockIdx.x] : (excl & 1u);
+  gptr<uint32_t> c = gmut<uint32_t>(A.c);
+#pragma unroll
+  for (int q = 0; q < kCrtPPT; ++q) {
+    const uint64_t x = t[q] + carry;
+    const uint64_t m = mb + lp0 + q;
+    if (m < A.npos) c[m] = (uint32_t)x;
+    carry = x >> 32;
+  }
+}
+
+hipError_t launch_crt32_carry(const CrtArgs& a, hipStream_t stream) {
+  const uint64_t nblk = (a.npos + kCrtBlock - 1) / kCrtBlock;
+  if (nblk == 0) return hipSuccess;
+  if (nblk > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crt32_phase1_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);
+  hipLaunchKernelGGL(crt_phase2_kernel, dim3(1), dim3(1024), 0, stream, a, (uint32_t)nblk);
+  hipLaunchKernelGGL(crt32_phase3_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);
+  return hipGetLastError();
+}
+
+// out[i] = in[i] mod p for 32-bit words: Function 8 with y = 1 (psi = floor(2^32 / p))
+// gives [0, 2p) for any word, one min finishes.
+__global__ void reduce_mod_kernel(const uint32_t* __restrict__ in, uint32_t* __restrict__ out, uint64_t n, uint32_t p,
+                                  uint32_t psi) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = in[i];
+    out[i] = red(x - __umulhi(x, psi) * p, p);
+  }
+}
+
+hipError_t launch_reduce_mod(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t p, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint32_t psi = (uint32_t)((1ull << 32) / p);
+  const int grid = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(reduce_mod_kernel, dim3(grid), dim3(256), 0, stream, in, out, n, p, psi);
+  return hipGetLastError();
+}
+
 }  // namespace nttgpu

@@ -12,6 +12,8 @@
 //    each wave, the result written from registers in the TFT order of step 4.  The
 //    inverse mirrors it; the fused product row pass runs both operands, the
 //    entry-wise product and the inverse in one workgroup.
+#include <string.h>
+
 #include "kernels.hpp"
 #include "ntt_wave.hpp"
 
@@ -149,7 +151,8 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
   const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
   if constexpr (!INV) {
     const gcptr<IN_T> in = gconst<IN_T>(uni(A.in)) + vec * A.in_stride;
-    const TwPair<T> sig = uni(ldtw<T>(&pc->sigma));
+    // scale 1: times sigma; 2: times 1 (reduction of words that may exceed p)
+    const TwPair<T> sig = uni(ldtw<T>(A.scale == 2 ? &pc->one : &pc->sigma));
     const bool scale = A.scale != 0;
 #pragma unroll 4
     for (int idx = tid; idx < cnt; idx += NT) {
@@ -197,7 +200,8 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
 // Two workgroups per CU (at most 64 VGPRs for 1024-thread 32-bit tiles) so that one
 // tile's HBM phases overlap the other's arithmetic.
 template <typename T, int NT, int TILELOG, int K, bool INV, typename IN_T>
-__global__ __launch_bounds__(NT, (NT == 1024 ? 8 : 4)) void col_wave_kernel(PassArgs A, uint64_t ntiles, int L2) {
+__global__ __launch_bounds__(NT, (NT == 1024 ? 8 : 4)) void col_wave_kernel(PassJobs J, uint64_t ntiles, int L2) {
+  const PassArgs& A = J.j[blockIdx.y];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
   const Arith<T> ar = arith_uni<T>(A.pc);
@@ -367,7 +371,8 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 
 template <typename T, int NT, int M, int KIND>
 __global__ __launch_bounds__(NT, (KIND == 2 ? (sizeof(T) == 4 && NT < 1024 ? 4 : 1) : (sizeof(T) == 4 ? 8 : 4)))
-void row_wave_kernel(PassArgs A, uint64_t nrows) {
+void row_wave_kernel(PassJobs J, uint64_t nrows) {
+  const PassArgs& A = J.j[blockIdx.y];
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
   T* sb = sa + lds_words(1 << M);
@@ -383,20 +388,20 @@ void row_wave_kernel(PassArgs A, uint64_t nrows) {
 static int grid_of(uint64_t items) { return (int)(items < 1048576ull ? items : 1048576ull); }
 
 template <typename T, int NT, int TILELOG, int K, bool INV, typename IN_T>
-static hipError_t launch_col_wave_k(const PassArgs& a, int L2, hipStream_t stream) {
+static hipError_t launch_col_wave_k(const PassJobs& a, int L2, hipStream_t stream) {
   constexpr int LC0 = TILELOG - K;
   const int LC = LC0 < L2 ? LC0 : L2;
-  const uint64_t ntiles = (uint64_t)a.batch << (L2 - LC);
+  const uint64_t ntiles = (uint64_t)a.j[0].batch << (L2 - LC);
   const size_t lds = (size_t)(1 << LC) * (lds_words(1 << K) + 1) * sizeof(T);
   auto k = col_wave_kernel<T, NT, TILELOG, K, INV, IN_T>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid_of(ntiles)), dim3(NT), lds, stream, a, ntiles, L2);
+  hipLaunchKernelGGL(k, dim3(grid_of(ntiles), a.n), dim3(NT), lds, stream, a, ntiles, L2);
   return hipGetLastError();
 }
 
 template <typename T, int NT, int TILELOG, bool INV, typename IN_T>
-static hipError_t launch_col_wave(const PassArgs& a, int L1, int L2, hipStream_t stream) {
+static hipError_t launch_col_wave(const PassJobs& a, int L1, int L2, hipStream_t stream) {
   switch (L1) {
 #define NTT_COL(KK) \
   case KK: return launch_col_wave_k<T, NT, TILELOG, KK, INV, IN_T>(a, L2, stream);
@@ -411,35 +416,66 @@ hipError_t launch_col_fwd_rounds(int word_bits, const PassArgs& a, int L1, int L
 hipError_t launch_col_inv_rounds(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_row_rounds(int word_bits, int kind, const PassArgs& a, int L1, int L2, hipStream_t stream);
 
-hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  if (L1 > 10) return launch_col_fwd_rounds(word_bits, a, L1, L2, stream);
+static PassJobs one_job(const PassArgs& a) {
+  PassJobs j;
+  memset(&j, 0, sizeof(j));
+  j.j[0] = a;
+  j.n = 1;
+  return j;
+}
+
+hipError_t launch_col_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
+  if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
+  if (L1 > 10) {
+    for (int i = 0; i < a.n; ++i) {
+      hipError_t e = launch_col_fwd_rounds(word_bits, a.j[i], L1, L2, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (word_bits == 32) {
-    if (a.in_u16) return launch_col_wave<uint32_t, 1024, 14, false, uint16_t>(a, L1, L2, stream);
+    if (a.j[0].in_u16) return launch_col_wave<uint32_t, 1024, 14, false, uint16_t>(a, L1, L2, stream);
     return launch_col_wave<uint32_t, 1024, 14, false, uint32_t>(a, L1, L2, stream);
   }
   return launch_col_wave<uint64_t, 512, 13, false, uint64_t>(a, L1, L2, stream);
 }
 
-hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  if (L1 > 10) return launch_col_inv_rounds(word_bits, a, L1, L2, stream);
+hipError_t launch_col_inv_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
+  if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
+  if (L1 > 10) {
+    for (int i = 0; i < a.n; ++i) {
+      hipError_t e = launch_col_inv_rounds(word_bits, a.j[i], L1, L2, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (word_bits == 32) return launch_col_wave<uint32_t, 1024, 14, true, uint32_t>(a, L1, L2, stream);
   return launch_col_wave<uint64_t, 512, 13, true, uint64_t>(a, L1, L2, stream);
 }
 
+hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  return launch_col_fwd_jobs(word_bits, one_job(a), L1, L2, stream);
+}
+
+hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  return launch_col_inv_jobs(word_bits, one_job(a), L1, L2, stream);
+}
+
 template <typename T, int NT, int M, int KIND>
-static hipError_t launch_row_wave(const PassArgs& a, int L1, hipStream_t stream) {
-  const uint64_t nrows = (uint64_t)a.batch << L1;
+static hipError_t launch_row_wave(const PassJobs& a, int L1, hipStream_t stream) {
+  const uint64_t nrows = (uint64_t)a.j[0].batch << L1;
   const size_t lds = (KIND == 2 ? 2 : 1) * (size_t)lds_words(1 << M) * sizeof(T);
   auto k = row_wave_kernel<T, NT, M, KIND>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(grid_of(nrows)), dim3(NT), lds, stream, a, nrows);
+  hipLaunchKernelGGL(k, dim3(grid_of(nrows), a.n), dim3(NT), lds, stream, a, nrows);
   return hipGetLastError();
 }
 
 // Rows of 2^12 .. 2^14 words (the split is a tuning choice): one wave per 1024-word block.
 template <int KIND>
-static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+static hipError_t launch_row_kind(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
+  if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
   if (word_bits == 32) {
     if (L2 == 14) return launch_row_wave<uint32_t, 1024, 14, KIND>(a, L1, stream);
     if (L2 == 13) return launch_row_wave<uint32_t, 512, 13, KIND>(a, L1, stream);
@@ -448,17 +484,24 @@ static hipError_t launch_row_kind(int word_bits, const PassArgs& a, int L1, int 
     if (L2 == 13) return launch_row_wave<uint64_t, 512, 13, KIND>(a, L1, stream);
     if (L2 == 12) return launch_row_wave<uint64_t, 256, 12, KIND>(a, L1, stream);
   }
-  return launch_row_rounds(word_bits, KIND, a, L1, L2, stream);
+  for (int i = 0; i < a.n; ++i) {
+    hipError_t e = launch_row_rounds(word_bits, KIND, a.j[i], L1, L2, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
-  return launch_row_kind<0>(word_bits, a, L1, L2, stream);
+  return launch_row_kind<0>(word_bits, one_job(a), L1, L2, stream);
 }
 hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool scale_ninv, hipStream_t stream) {
   (void)scale_ninv;  // the caller passes the twist table with n^-1 folded in when asked
-  return launch_row_kind<1>(word_bits, a, L1, L2, stream);
+  return launch_row_kind<1>(word_bits, one_job(a), L1, L2, stream);
 }
 hipError_t launch_row_polymul(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
+  return launch_row_kind<2>(word_bits, one_job(a), L1, L2, stream);
+}
+hipError_t launch_row_polymul_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
   return launch_row_kind<2>(word_bits, a, L1, L2, stream);
 }
 

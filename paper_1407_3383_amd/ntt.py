@@ -43,7 +43,7 @@ EXPORTS = (
     "ntt_forward", "ntt_inverse", "polymul_workspace_bytes", "polymul_modp",
     "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
-    "intmul_workspace_bytes", "intmul_crt",
+    "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
 )
@@ -104,6 +104,9 @@ def load(path: str = LIB_PATH):
         "polymul_batch_destroy": (ci, [vp]),
         "intmul_workspace_bytes": (sz, [sz, sz]),
         "intmul_crt": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
+        "intmul_chunk_bits": (ci, [sz, sz]),
+        "intmul32_workspace_bytes": (sz, [sz, sz]),
+        "intmul_crt32": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
         "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
         "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
         "ntt_tune_clear": (ci, []),
@@ -354,6 +357,24 @@ def intmul(a16, b16, out=None, stream=None, workspace=None):
     _check(L.intmul_crt(_ptr(a16), na, _ptr(b16), nb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                         _stream(stream)), "intmul_crt")
     return out
+
+
+def intmul32(a32, b32, out=None, stream=None, workspace=None):
+    """Product of two little-endian 32-bit-chunk integers -> na + nb 32-bit limbs."""
+    torch = _torch()
+    L = load()
+    na, nb = a32.numel(), b32.numel()
+    if out is None:
+        out = torch.empty(na + nb, dtype=torch.int32, device=a32.device)
+    need = L.intmul32_workspace_bytes(na, nb)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, a32.device)
+    _check(L.intmul_crt32(_ptr(a32), na, _ptr(b32), nb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                          _stream(stream)), "intmul_crt32")
+    return out
+
+
+def intmul_chunk_bits(na16: int, nb16: int) -> int:
+    return int(load().intmul_chunk_bits(na16, nb16))
 
 
 # ----------------------------------------------------------------------------- graphs

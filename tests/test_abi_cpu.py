@@ -123,3 +123,26 @@ def test_workspace_sizes(lib):
     descs[1] = ntt.PolymulDesc(2013265921, 16, 1 << 17, 16, 1 << 17, 16)
     ws = lib.polymul_batch_workspace_bytes(descs, 2)
     assert ws >= 2 * 4 * (1 << 18)
+
+
+def test_intmul_chunk_bits_rule(lib):
+    # section 5.3's rule with p1 p2 p3 ~ 2^86.02: h = 32 while 64 + ceil(log2(d + 1)) <= 86
+    assert ntt.intmul_chunk_bits(1 << 21, 1 << 21) == 32        # d = 2^20 chunks of 32 bits: H = 85
+    assert ntt.intmul_chunk_bits(2, 1) == 32
+    big = (1 << 23) - 2                                          # d = 2^22 - 1 chunks: H = 64 + 22 = 86 < 86.02
+    assert ntt.intmul_chunk_bits(big, big) == 32
+    # d = 2^22 chunks: H = 64 + 23 = 87 is too many bits; 16-bit chunks: H = 32 + 23 fits
+    assert ntt.intmul_chunk_bits((1 << 23) - 1, 1) == 16
+    assert ntt.intmul_chunk_bits(1 << 24, 1 << 24) == 0          # no chunk size fits the transform lengths
+
+
+def test_intmul32_argument_errors_and_sizes(lib):
+    vp = ctypes.c_void_p
+    one = vp(16)
+    # coefficients could reach p1 p2 p3: min(na, nb) too large
+    assert lib.intmul_crt32(one, 4300000, one, 4300000, one, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.intmul32_workspace_bytes(4300000, 4300000) == 0
+    assert lib.intmul_crt32(one, 1 << 22, one, (1 << 22) + 2, one, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.intmul_crt32(one, 10, one, 10, one, None, 0, None) == ntt.NTT_ENOMEM
+    assert lib.intmul_crt32(vp(2), 10, one, 10, one, None, 0, None) == ntt.NTT_EINVAL   # misaligned
+    assert lib.intmul32_workspace_bytes(1 << 20, 1 << 20) >= 3 * 4 * ((1 << 21) - 1)

@@ -52,3 +52,42 @@ def test_intmul_full_size_modular_checks():
     # low and high limbs against the exact product
     ref = oracle.intmul_pyint(a, b)
     assert_equal_u(c, ref, "intmul full size")
+
+
+# ---------------------------------------------------------------- 32-bit chunks (section 5.3's h)
+
+def _gpu_intmul32(a16, b16):
+    torch_cuda()
+    a32 = np.ascontiguousarray(a16).view("<u4")
+    b32 = np.ascontiguousarray(b16).view("<u4")
+    return ntt.to_numpy(ntt.intmul32(ntt.to_device(a32.astype(np.uint32)), ntt.to_device(b32.astype(np.uint32))))
+
+
+@pytest.mark.parametrize("na,nb", [(2, 2), (2, 4), (6, 14), (128, 128), (2000, 1998), (8192, 8192),
+                                   (40000, 6), ((1 << 15), (1 << 15)), (70000, 65000), (1 << 17, 1 << 16)])
+def test_intmul32_against_python_int(na, nb):
+    # na, nb 16-bit limbs (even): the same integers read as 32-bit chunks
+    a = inputs.limbs16(na, inputs.CFG_TEST, 3000 + na, 0)
+    b = inputs.limbs16(nb, inputs.CFG_TEST, 3000 + nb, 1)
+    say("intmul32 na16=%d nb16=%d" % (na, nb))
+    got = _gpu_intmul32(a, b)
+    assert got.size == (na + nb) // 2
+    assert_equal_u(got, oracle.intmul_pyint(a, b), "intmul32")
+
+
+def test_intmul32_all_ones_closed_form():
+    n = 30000  # 32-bit chunks of all ones
+    torch_cuda()
+    ff = np.full(n, 0xFFFFFFFF, dtype=np.uint32)
+    c = ntt.to_numpy(ntt.intmul32(ntt.to_device(ff), ntt.to_device(ff)))
+    v = int.from_bytes(c.astype("<u4").tobytes(), "little")
+    assert v == (1 << (64 * n)) - (1 << (32 * n + 1)) + 1
+
+
+def test_intmul32_equals_16_bit_path_full_size():
+    # the integer product configuration (2^21 16-bit limbs each) through both chunk sizes
+    a, b = inputs.intmul_inputs()
+    say("intmul32 full size")
+    c32 = _gpu_intmul32(a, b)
+    assert_equal_u(c32, oracle.intmul_pyint(a, b), "32-bit chunks, full size, vs Python int")
+    assert_equal_u(c32, _gpu_intmul(a, b), "32-bit chunks vs 16-bit limbs")
