@@ -10,11 +10,20 @@ namespace nttgpu {
 // d = log2 N - m is the split depth: the product runs as 2^d sub-problems of length
 // 2^m (section 5.1's Algorithm 1 with n1 = 2^d), each sub-problem h starting from the
 // fold sum_k a[j + k 2^m] psi_h^k, psi_h = w_{2^d}^([h]_d).
+//
+// Truncation (the TFT of section 5.1 at sub-problem granularity): a product with
+// lc <= lambda S coefficients needs only the sub-problems h < lambda = ceil(lc / S),
+// the first lambda values of Algorithm 1's step-1 TFT of size 2^d.  The partials of
+// the sub-problems h >= lambda are then fixed by the zero coefficients c_k = 0,
+// k >= lambda, of every recombined position: u_miss = T u_known, with T the matrix
+// below (entry (r, c) multiplies u_c into u_(lambda + r)).
 template <typename T>
 struct PolyConst {
   T p, p2, pinv, lazy;  // lazy = 1 when 4p < 2^bits(T)
   TwPair<T> fa[4][4];   // psi_h^k
   TwPair<T> fb[4][4];   // psi_h^k * sigma, sigma = 2^bits(T) / N mod p (Montgomery scale)
+  TwPair<T> tft2[3];        // d = 2, lambda = 3: 1 x 3
+  TwPair<T> tft3[3][3][7];  // d = 3, lambda = 5, 6, 7: (8 - lambda) x lambda
 };
 
 // One product in a fused launch.

@@ -354,6 +354,65 @@ int build_plan_tables(ntt_plan* pl) {
       }
     }
   }
+  {
+    // completion of truncated products (d = 2 and 3): the recombination map W of the
+    // last d inverse stages (TWI[2^t + blk]), then T = -A^-1 B with A = W[k >= lam][h >= lam],
+    // B = W[k >= lam][h < lam]
+    const int K8 = (int)std::min<size_t>(twi.size(), 8);
+    for (int d = 2; d <= 3 && (1 << d) <= K8; ++d) {
+      const int n = 1 << d;
+      std::vector<std::vector<uint64_t>> W(n, std::vector<uint64_t>(n, 0));
+      for (int hcol = 0; hcol < n; ++hcol) {
+        std::vector<uint64_t> u(n, 0);
+        u[hcol] = 1;
+        for (int t = d - 1; t >= 0; --t) {
+          const int half = 1 << (d - 1 - t);
+          for (int blk = 0; blk < (1 << t); ++blk) {
+            const uint64_t w = (uint64_t)twi[(1 << t) + blk].w;
+            for (int i = 0; i < half; ++i) {
+              const int x = blk * 2 * half + i, y = x + half;
+              const uint64_t X = u[x], Y = u[y];
+              u[x] = (X + Y) % p;
+              u[y] = mulmod((X + p - Y) % p, w, p);
+            }
+          }
+        }
+        for (int k = 0; k < n; ++k) W[k][hcol] = u[k];
+      }
+      for (int lam = n / 2 + 1; lam < n; ++lam) {
+        const int m = n - lam;
+        // augmented [A | B], solved in place by Gauss-Jordan elimination mod p
+        std::vector<std::vector<uint64_t>> G(m, std::vector<uint64_t>(m + lam, 0));
+        for (int r = 0; r < m; ++r) {
+          for (int cidx = 0; cidx < m; ++cidx) G[r][cidx] = W[lam + r][lam + cidx];
+          for (int cidx = 0; cidx < lam; ++cidx) G[r][m + cidx] = W[lam + r][cidx];
+        }
+        bool ok_solve = true;
+        for (int col = 0; col < m && ok_solve; ++col) {
+          int piv = -1;
+          for (int r = col; r < m; ++r)
+            if (G[r][col]) { piv = r; break; }
+          if (piv < 0) { ok_solve = false; break; }
+          std::swap(G[piv], G[col]);
+          const uint64_t inv = invmod(G[col][col], p);
+          for (auto& e : G[col]) e = mulmod(e, inv, p);
+          for (int r = 0; r < m; ++r) {
+            if (r == col || !G[r][col]) continue;
+            const uint64_t f = G[r][col];
+            for (int cidx = 0; cidx < m + lam; ++cidx) G[r][cidx] = (G[r][cidx] + p - mulmod(f, G[col][cidx], p)) % p;
+          }
+        }
+        if (!ok_solve) return fail(NTT_EDEVICE, "truncated-product completion matrix is singular (p = %llu, d = %d)",
+                                   (unsigned long long)p, d);
+        for (int r = 0; r < m; ++r)
+          for (int cidx = 0; cidx < lam; ++cidx) {
+            const uint64_t tv = (p - G[r][m + cidx]) % p;  // T = -A^-1 B
+            if (d == 2) pc.tft2[cidx] = pair_of<T>(tv, p);
+            else pc.tft3[lam - 5][r][cidx] = pair_of<T>(tv, p);
+          }
+      }
+    }
+  }
   const size_t o_pc = blob.add(&pc, sizeof(pc));
 
   // Two-pass constants and twist tables.
@@ -995,6 +1054,10 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
       x.tw = pl->tw;
       x.twi = pl->twi;
       x.park = workspace;
+      {
+        const size_t S = (size_t)1 << (s.L - s.split);
+        x.lam = (uint32_t)std::min<size_t>((size_t)1 << s.split, (s.lc + S - 1) / S);
+      }
       HIP_TRY(launch_split(s.wb, x, s.L, s.split, stream));
       return ok();
     }

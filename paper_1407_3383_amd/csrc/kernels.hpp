@@ -107,6 +107,8 @@ struct SplitArgs {
   const void* tw;
   const void* twi;
   void* park;
+  uint32_t lam;  // sub-problems computed: ceil(lc / S) (TFT truncation), the rest completed
+  uint32_t pad;
 };
 bool split_supported(int word_bits, int log2n, int d);
 hipError_t launch_split(int word_bits, const SplitArgs& a, int log2n, int d, hipStream_t stream);

@@ -251,6 +251,9 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   const int nsub = 1 << d;
   const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
   const bool more_terms = nsub > 2 && (uint64_t)2 * S < (la > lb ? la : lb);
+  // TFT truncation: only the sub-problems h < lam hold outputs below lc; the last
+  // partial is completed from the zero coefficients when lam < nsub (d = 2, lam = 3)
+  const int lam = (int)((lc + S - 1) / S < (uint64_t)nsub ? (lc + S - 1) / S : (uint64_t)nsub);
   T* const sv2[2] = {sa, sb};
 
   // G' (top inverse stages) of sub-problem hp on the thread's clusters; hands each
@@ -290,7 +293,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       }
   };
   request_fold_inputs();
-  for (int h = 0; h < nsub; ++h) {
+  for (int h = 0; h < lam; ++h) {
     const int t0 = opaque_tid();
     // ---- boundary phase: G' of h-1 and park, fold + G of h
     if constexpr (MAXD > 0) {
@@ -359,7 +362,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       }
       inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
     }
-    if (h + 1 < nsub) request_fold_inputs();
+    if (h + 1 < lam) request_fold_inputs();
     __syncthreads();
   }
   // ---- last boundary: G' of the last sub-problem and the recombination
@@ -375,18 +378,21 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
           const int j = t0 + i * NT + 1024 * cc;
           q0[e] = d >= 1 ? park[j] : (T)0;
           q1[e] = d >= 2 ? park[S + j] : (T)0;
-          q2[e] = d >= 2 ? park[2 * S + j] : (T)0;
+          q2[e] = (d >= 2 && lam == 4) ? park[2 * S + j] : (T)0;
         }
     }
-    // recombination twiddles, loaded before any output store (a load placed after a
-    // store would wait for the store as well)
-    TwPair<T> w1, w2, w3;
+    // recombination twiddles and completion factors, loaded before any output store
+    // (a load placed after a store would wait for the store as well)
+    TwPair<T> w1, w2, w3, k0, k1, k2;
     if constexpr (MAXD > 0) {
       w1 = uni(ldtw<T>(twi + 1));
       w2 = uni(ldtw<T>(twi + 2));
       w3 = uni(ldtw<T>(twi + 3));
+      k0 = uni(ldtw<T>(&pc->tft2[0]));
+      k1 = uni(ldtw<T>(&pc->tft2[1]));
+      k2 = uni(ldtw<T>(&pc->tft2[2]));
     }
-    finish(nsub - 1, t0, [&](int e, int j, T v) {
+    finish(lam - 1, t0, [&](int e, int j, T v) {
       const uint64_t jj = (uint64_t)j;
       if (d == 0) {
         if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, v);
@@ -399,7 +405,16 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         }
       } else {
         if constexpr (MAXD > 1) {
-          T u0 = q0[e], u1 = q1[e], u2 = q2[e], u3 = v;
+          T u0 = q0[e], u1 = q1[e], u2, u3;
+          if (lam == 4) {
+            u2 = q2[e];
+            u3 = v;
+          } else {  // u3 = k0 u0 + k1 u1 + k2 u2: the partial that makes c_3 vanish
+            u2 = v;
+            const T s0 = ar.red1(ar.shoup_u(u0, k0.w, k0.ws)), s1 = ar.red1(ar.shoup_u(u1, k1.w, k1.ws));
+            const T s2 = ar.red1(ar.shoup_u(u2, k2.w, k2.ws));
+            u3 = ar.red1(ar.red1(s0 + s1) + s2);
+          }
           gs_bfly<LAZY, true>(ar, u0, u1, w2);
           gs_bfly<LAZY, true>(ar, u2, u3, w3);
           gs_bfly<LAZY, true>(ar, u0, u2, w1);

@@ -124,8 +124,29 @@ __device__ __forceinline__ void recombine_one(const SplitArgs& A, const Arith<T>
   const gcptr<T> park = gconst<T>(A.park);
   const gcptr<TwPair<T>> twi = gconst<TwPair<T>>(A.twi);
   T u[K];
+  const int lam = (int)A.lam;
 #pragma unroll
-  for (int k = 0; k < K; ++k) u[k] = park[(uint64_t)k * S + j];
+  for (int k = 0; k < K; ++k) u[k] = k < lam ? park[(uint64_t)k * S + j] : (T)0;
+  // TFT truncation: the partials h >= lam (not computed) are the combinations of the
+  // computed ones that make the coefficients k >= lam vanish
+  if constexpr (D >= 2) {
+    if (lam < K) {
+      const gcptr<PolyConst<T>> pc = gconst<PolyConst<T>>(A.cst);
+#pragma unroll
+      for (int r = 0; r < K / 2 - 1; ++r) {
+        const int row = lam + r;
+        if (row >= K) break;
+        T acc = 0;
+#pragma unroll
+        for (int cidx = 0; cidx < K - 1; ++cidx) {
+          if (cidx >= lam) break;
+          const TwPair<T> f = uni(ldtw<T>(D == 2 ? &pc->tft2[cidx] : &pc->tft3[lam - 5][r][cidx]));
+          acc = ar.red1(acc + ar.red1(ar.shoup_u(u[cidx], f.w, f.ws)));
+        }
+        u[row] = acc;
+      }
+    }
+  }
 #pragma unroll
   for (int t = D - 1; t >= 0; --t) {
     const int half = 1 << (D - 1 - t);
@@ -166,7 +187,7 @@ static hipError_t launch_split_md(const SplitArgs& a, hipStream_t stream) {
   auto k = polymul_split_kernel<T, NT, M, D>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(1u << D), dim3(NT), lds, stream, a);
+  hipLaunchKernelGGL(k, dim3(a.lam), dim3(NT), lds, stream, a);
   hipLaunchKernelGGL((split_recombine_kernel<T, D>), dim3(((1u << M) + 255) / 256), dim3(256), 0, stream, a, M);
   return hipGetLastError();
 }
@@ -182,6 +203,7 @@ static hipError_t launch_split_m(const SplitArgs& a, int d, hipStream_t stream) 
 }
 
 bool split_supported(int word_bits, int log2n, int d) {
+  // (the launch computes the sub-problems h < lam only, lam = ceil(lc / 2^(log2n - d)))
   const int M = log2n - d;
   if (d < 1 || d > 3) return false;
   return M >= 10 && M <= (word_bits == 32 ? 13 : 12);

@@ -103,3 +103,22 @@ def test_polymul_batch_mixed_primes_and_sizes():
     outs = ntt.polymul_batch(pairs, [s[0] for s in specs])
     for i, (o, r) in enumerate(zip(outs, ref)):
         assert_equal_u(ntt.to_numpy(o), r, "mixed item %d" % i)
+
+
+# TFT truncation in the fused batch kernel: 2^16-point products with lc <= 3 * 2^14
+# compute 3 of their 4 sub-problems and complete the fourth from the zero coefficients
+@pytest.mark.parametrize("la,lb", [(16385, 16385), (20000, 18000), (24576, 24576), (24577, 24576), (24577, 24577),
+                                   (40000, 2), (2, 49000)])
+def test_fused_truncated_products(la, lb):
+    torch_cuda()
+    p = 2013265921
+    pairs, outs, want = [], [], []
+    for k in range(3):
+        a = inputs.residues(p, la, inputs.CFG_TEST, 1700 + k, 0)
+        b = inputs.residues(p, lb, inputs.CFG_TEST, 1700 + k, 1)
+        pairs.append((ntt.to_device(a), ntt.to_device(b)))
+        want.append(oracle.polymul_ntt(a, b, p, 31))
+    say("fused batch truncated products la=%d lb=%d" % (la, lb))
+    got = ntt.polymul_batch(pairs, [p] * 3)
+    for k in range(3):
+        assert_equal_u(ntt.to_numpy(got[k]), want[k], "fused truncated product %d" % k)

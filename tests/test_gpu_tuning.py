@@ -129,3 +129,20 @@ def test_autotuner_quick_run_writes_loadable_choices(fresh, tmp_path):
     keys = [ln.split()[0] for ln in open(out) if ln.split() and not ln.lstrip().startswith("#")]
     assert "fused.single.max.w32" in keys and "split.w32.L24" in keys
     assert all(ntt.tune_get(k) is not None for k in keys)
+
+
+# TFT truncation: products whose lc leaves the top sub-problems without outputs
+@pytest.mark.parametrize("p,la,lb,L,d", [
+    (998244353, 20000, 20000, 16, 3), (998244353, 24000, 24000, 16, 3), (2013265921, 28000, 28000, 16, 3),
+    (998244353, 9000, 9000, 15, 2), (469762049, 12000, 8000, 15, 2), (2013265921, 40000, 2, 16, 3),
+    (4611685941117976577, 9000, 9000, 15, 3), (4611685941117976577, 5000, 4000, 14, 2)])
+def test_split_truncated_products(fresh, p, la, lb, L, d):
+    a = inputs.residues(p, la, inputs.CFG_TEST, 1600 + la, 0)
+    b = inputs.residues(p, lb, inputs.CFG_TEST, 1600 + lb, 1)
+    assert (la + lb - 2).bit_length() == L
+    want = oracle.polymul_ntt(a, b, p, numtheory.smallest_generator(p))
+    w = ntt.word_bits(p)
+    ntt.tune_set("single.split.w%d.L%d" % (w, L), d)
+    S = 1 << (L - d)
+    say("split product p=%d la=%d lb=%d: %d of %d sub-problems" % (p, la, lb, -(-(la + lb - 1) // S), 1 << d))
+    assert_equal_u(ntt.to_numpy(ntt.polymul(ntt.to_device(a), ntt.to_device(b), p)), want, "truncated split product")
