@@ -154,6 +154,28 @@ def run(name, args):
                      {"workload": "product of the same two 2^25-bit integers as 2^20 chunks of 32 bits (h = 32 by "
                                   "the chunk-size rule), primes 998244353, 469762049, 167772161, transform length 2^21"},
                      {"ms_per_product": round(ms, 4), "chunk_bits": ntt.intmul_chunk_bits(a.size, b.size)})
+    if name == "tft":
+        # TFT truncation at sub-problem granularity: 1024 products mod 2013265921 of
+        # operands of length 20000 (lc = 39999 <= 3 * 2^14: 3 of the 4 sub-problems of the
+        # 2^16-point transform) beside the same batch at full length 2^15 (4 of 4)
+        P = 2013265921
+        res = {}
+        for la in (20000, 1 << 15):
+            _, A, B = inputs.polymul_batch_inputs(1024, la, P)
+            dA, dB = ntt.to_device(A), ntt.to_device(B)
+            dC = torch.empty((1024, 2 * la - 1), dtype=torch.int32, device="cuda")
+            bt = ntt.Batch.rows(dA, dB, dC, P)
+            ms, kms = _time(lambda: bt(stream), stream, max(args.steps, 50), 10)
+            res[la] = kms
+            del bt, dA, dB, dC
+        full = 1024 * 3 * (1 << 15) * 16
+        _log("tft: %.4f ms truncated, %.4f ms full" % (res[20000], res[1 << 15]))
+        return _line("batched polymul with TFT truncation, 1024 x (20000 x 20000) mod 2013265921 (ms per launch)",
+                     res[20000], "ms", res[20000], max(args.steps, 50), 10,
+                     {"workload": "1024 products of length-20000 operands, transform length 2^16, 3 of 4 sub-problems"},
+                     {"higher_is_better": False, "full_length_ms": round(res[1 << 15], 4),
+                      "time_ratio": round(res[20000] / res[1 << 15], 4),
+                      "note": "untruncated, both batches would take the same time (same transform length)"})
     if name == "serve":
         return run_serve(args)
     raise ValueError(name)
