@@ -154,20 +154,73 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     // scale 1: times sigma; 2: times 1 (reduction of words that may exceed p)
     const TwPair<T> sig = uni(ldtw<T>(A.scale == 2 ? &pc->one : &pc->sigma));
     const bool scale = A.scale != 0;
+    bool vec4 = false;
+    if constexpr (sizeof(T) == 4 && sizeof(IN_T) <= 4)
+      vec4 = C >= 4 && ((uintptr_t)(const IN_T*)in % (4 * sizeof(IN_T))) == 0 && (A.in_stride % 4) == 0;
+    if (vec4) {
+      // runs of 4 columns as one 16-byte (8-byte for 16-bit limbs) access per thread
+      const int lc4 = LC - 2;
+#pragma unroll 2
+      for (int idx = tid; idx < (cnt >> 2); idx += NT) {
+        const uint32_t r = (uint32_t)idx >> lc4, cc = ((uint32_t)idx & ((C >> 2) - 1)) << 2;
+        const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+        T x[4];
+        if (gi + 3 < A.valid) {
+          if constexpr (sizeof(IN_T) == 4) {
+            const uint4 q = *(const uint4*)((const IN_T*)in + gi);
+            x[0] = q.x;
+            x[1] = q.y;
+            x[2] = q.z;
+            x[3] = q.w;
+          } else {
+            const uint2 q = *(const uint2*)((const IN_T*)in + gi);
+            x[0] = q.x & 0xFFFFu;
+            x[1] = q.x >> 16;
+            x[2] = q.y & 0xFFFFu;
+            x[3] = q.y >> 16;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[i] = gi + i < A.valid ? (T)in[gi + i] : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          T y = x[i];
+          if (scale) y = ar.red1(ar.shoup_u(y, sig.w, sig.ws));
+          s[(cc + i) * VS + lidx(r)] = y;
+        }
+      }
+    } else {
 #pragma unroll 4
-    for (int idx = tid; idx < cnt; idx += NT) {
-      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
-      const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
-      T x = gi < A.valid ? (T)in[gi] : (T)0;
-      if (scale) x = ar.red1(ar.shoup_u(x, sig.w, sig.ws));
-      s[cc * VS + lidx(r)] = x;
+      for (int idx = tid; idx < cnt; idx += NT) {
+        const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+        const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+        T x = gi < A.valid ? (T)in[gi] : (T)0;
+        if (scale) x = ar.red1(ar.shoup_u(x, sig.w, sig.ws));
+        s[cc * VS + lidx(r)] = x;
+      }
     }
   } else {
     const gcptr<T> in = gconst<T>(uni(A.in)) + vec * A.in_stride;
+    bool vec4 = false;
+    if constexpr (sizeof(T) == 4) vec4 = C >= 4 && ((uintptr_t)(const T*)in % 16) == 0 && (A.in_stride % 4) == 0;
+    if (vec4) {
+      const int lc4 = LC - 2;
+#pragma unroll 2
+      for (int idx = tid; idx < (cnt >> 2); idx += NT) {
+        const uint32_t r = (uint32_t)idx >> lc4, cc = ((uint32_t)idx & ((C >> 2) - 1)) << 2;
+        const uint4 q = *(const uint4*)((const T*)in + ((uint64_t)r << L2) + col0 + cc);
+        s[cc * VS + lidx(r)] = q.x;
+        s[(cc + 1) * VS + lidx(r)] = q.y;
+        s[(cc + 2) * VS + lidx(r)] = q.z;
+        s[(cc + 3) * VS + lidx(r)] = q.w;
+      }
+    } else {
 #pragma unroll 4
-    for (int idx = tid; idx < cnt; idx += NT) {
-      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
-      s[cc * VS + lidx(r)] = in[((uint64_t)r << L2) + col0 + cc];
+      for (int idx = tid; idx < cnt; idx += NT) {
+        const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+        s[cc * VS + lidx(r)] = in[((uint64_t)r << L2) + col0 + cc];
+      }
     }
   }
   __syncthreads();
@@ -183,15 +236,44 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
   }
   __syncthreads();
   const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride;
+  bool vec4o = false;
+  if constexpr (sizeof(T) == 4) vec4o = C >= 4 && ((uintptr_t)(T*)out % 16) == 0 && (A.out_stride % 4) == 0;
+  if (vec4o) {
+    const int lc4 = LC - 2;
+#pragma unroll 2
+    for (int idx = tid; idx < (cnt >> 2); idx += NT) {
+      const uint32_t r = (uint32_t)idx >> lc4, cc = ((uint32_t)idx & ((C >> 2) - 1)) << 2;
+      const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+      T x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        x[i] = s[(cc + i) * VS + lidx(r)];
+        if constexpr (INV) x[i] = canon_from_inv<LAZY>(ar, x[i]);
+      }
+      if (!INV || gi + 3 < A.valid) {
+        uint4 q;
+        q.x = x[0];
+        q.y = x[1];
+        q.z = x[2];
+        q.w = x[3];
+        *(uint4*)((T*)out + gi) = q;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (gi + i < A.valid) out[gi + i] = x[i];
+      }
+    }
+  } else {
 #pragma unroll 4
-  for (int idx = tid; idx < cnt; idx += NT) {
-    const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
-    const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
-    const T x = s[cc * VS + lidx(r)];
-    if constexpr (INV) {
-      if (gi < A.valid) out[gi] = canon_from_inv<LAZY>(ar, x);
-    } else {
-      out[gi] = x;
+    for (int idx = tid; idx < cnt; idx += NT) {
+      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+      const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+      const T x = s[cc * VS + lidx(r)];
+      if constexpr (INV) {
+        if (gi < A.valid) out[gi] = canon_from_inv<LAZY>(ar, x);
+      } else {
+        out[gi] = x;
+      }
     }
   }
   __syncthreads();
