@@ -200,28 +200,43 @@ def run_serve(args):
                 for (p, L, rid), (a, b), t in zip(specs, ops, arrivals)]
 
     budget = 8 << 30
-    # warm the plan cache and the kernels
+    # the Python request loop, for comparison (everything queued at t = 0)
     warm = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
     warm.run(make([0.0] * n), realtime=False)
-    sat = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    pysat = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    pywall = pysat.run(make([0.0] * n), realtime=False)
+    # the native request loop (ntt_server_*): the measured one
+    Server = serve.NativeServer
+    warm = Server(budget, streams=4, max_batch=64, keep_results=False)
+    warm.run(make([0.0] * n), realtime=False)
+    warm.close()
+    sat = Server(budget, streams=4, max_batch=64, keep_results=False)
     wall = sat.run(make([0.0] * n), realtime=False)
+    sat.close()
     capacity = n / wall
+    # the same with every product copied back to host memory
+    back = Server(budget, streams=4, max_batch=64, keep_results=True)
+    wall_back = back.run(make([0.0] * n), realtime=False)
+    back.close()
     out = {"metric": "serving mix: p50/p99 latency and throughput", "value": round(capacity, 2), "unit": "requests/s",
            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
            "config": {"workload": "%d polymul requests, L = floor(2^U(8,20)), p uniform over {998244353, 2013265921, %d}" % (n, p62),
-                      "hbm_budget_bytes": budget, "streams": 4},
+                      "hbm_budget_bytes": budget, "streams": 4, "loop": "native (ntt_server_*)"},
            "saturated": {"requests_per_s": round(capacity, 2), "Gbfly_per_s": round(total_bfly / wall / 1e9, 2),
-                         **serve.latency_stats(sat.completed)}}
+                         **serve.latency_stats(sat.completed)},
+           "saturated_with_copy_back": {"requests_per_s": round(n / wall_back, 2), **serve.latency_stats(back.completed)},
+           "python_loop_saturated": {"requests_per_s": round(n / pywall, 2), **serve.latency_stats(pysat.completed)}}
     levels = {}
     for frac in (0.5, 0.8, 0.95):
         arr = inputs.poisson_arrivals(n, frac * capacity, int(frac * 100))
-        srv = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+        srv = Server(budget, streams=4, max_batch=64, keep_results=False)
         w = srv.run(make(arr), realtime=True)
+        srv.close()
         st = serve.latency_stats(srv.completed)
         levels[str(frac)] = {"offered_rps": round(frac * capacity, 2), "achieved_rps": round(n / w, 2),
                              "Gbfly_per_s": round(total_bfly / w / 1e9, 2), "max_inflight_batches": srv.max_inflight_batches,
-                             "overlapped_admissions": srv.overlapped_admissions, **st}
+                             **st}
         _log("serve at %.2f x capacity: p50 %.3f ms, p99 %.3f ms" % (frac, st["p50_ms"], st["p99_ms"]))
     out["poisson"] = levels
     # the same stream with every 10th request an integer product of L 16-bit limbs
@@ -235,11 +250,13 @@ def run_serve(args):
             b = inputs.limbs16(L, inputs.CFG_SERVE, r.rid, 1)
             reqs[k] = serve.Request(r.rid, 0, a, b, arrival=r.arrival, kind="int")
         return reqs
-    warm = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    warm = Server(budget, streams=4, max_batch=64, keep_results=False)
     warm.run(make_mixed([0.0] * n), realtime=False)
+    warm.close()
     arr = inputs.poisson_arrivals(n, 0.8 * capacity, 80)
-    srv = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
+    srv = Server(budget, streams=4, max_batch=64, keep_results=False)
     w = srv.run(make_mixed(arr), realtime=True)
+    srv.close()
     st = serve.latency_stats(srv.completed)
     ints = [r for r in srv.completed if r.kind == "int"]
     out["with_integer_products"] = {"share": 0.1, "offered_rps": round(0.8 * capacity, 2), "achieved_rps": round(n / w, 2),

@@ -241,6 +241,35 @@ size_t intmul_workspace_bytes(size_t na, size_t nb);
 int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint32_t* c, void* workspace,
                size_t ws_bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop on the current device: requests (polynomial products mod p with
+ * host residue vectors, kind 0; integer products of host 16-bit limbs, kind 1) are
+ * queued by ntt_server_submit and served by ntt_server_progress, which (1) completes
+ * the batches whose work has finished, copying each product into the request's host
+ * buffer c (la + lb - 1 residues, or ceil((la + lb) / 2) 32-bit limbs) and reporting
+ * the request ids, and (2) admits pending requests in arrival order while the HBM
+ * budget has room: consecutive polynomial requests form one polymul_modp_batch call,
+ * an integer product one intmul_crt call, each batch with one upload and one download
+ * through page-locked staging, on one of `streams` streams (default priority).
+ * Batches in flight overlap on the device (at most 2 per stream).  c == NULL: the
+ * product is computed but not copied back.  The server owns one device buffer of
+ * hbm_budget bytes (the arena) and its page-locked staging (128 MiB per batch in
+ * flight, allocated at creation); the caller keeps a, b and c valid until the
+ * request's id is reported.  One host thread drives a server.
+ * Errors: NTT_EINVAL (arguments), NTT_ENOTPRIME / NTT_ENOROOT (kind 0 prime or length),
+ * NTT_ENOMEM (a request that cannot fit the budget even alone; allocation failures),
+ * NTT_EDEVICE (a device failure: destroy the server). */
+typedef struct ntt_server ntt_server;
+int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t max_batch);
+int ntt_server_submit(ntt_server* server, uint64_t id, int kind, uint64_t p, const void* a, size_t la,
+                      const void* b, size_t lb, void* c);
+/* done_ids receives at most cap ids; *ndone how many. */
+int ntt_server_progress(ntt_server* server, uint64_t* done_ids, size_t cap, size_t* ndone);
+int ntt_server_stats(const ntt_server* server, size_t* pending, size_t* inflight, size_t* arena_used,
+                     size_t* max_inflight);
+/* Waits for the work in flight, then frees everything the server owns. */
+int ntt_server_destroy(ntt_server* server);
+
 /* Section 5.3's choice of the chunk size h for integers of na16 and nb16 16-bit
  * limbs: the largest h in {32, 16} with 2^(2h + ceil(log2(d + 1))) < p1 p2 p3 (d the
  * larger chunk count) and d_a + d_b - 1 <= 2^23; 0 when neither fits. */

@@ -1,0 +1,458 @@
+// Native serving loop: continuous batching of polynomial and integer products by HBM
+// budget (the batching of section 2.2's Remark 6 applied to a request stream).
+//
+// Requests carry host operands.  progress() completes finished batches (their results
+// are copied back to the requests' host buffers), then admits pending requests in
+// arrival order while the device arena has room: consecutive polynomial requests form
+// one batched call (polymul_modp_batch: one fused launch per size class), an integer
+// product is one intmul_crt call.  Each batch owns one arena block [operands | products
+// | workspace] and one page-locked staging block [operands | products], so a batch costs
+// one upload, one library call and one download, all asynchronous on one of the
+// server's streams, followed by an event.  Batches on different streams overlap on the
+// device.  The host copies into and out of the staging blocks run on a small pool of
+// copy threads (one thread's memcpy is well below the host's memory bandwidth and would
+// bound the loop).  Not thread-safe: one host thread drives a server.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/ntt_mi355x.h"
+
+namespace {
+
+const size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Req {
+  uint64_t id;
+  int kind;  // 0 polynomial product mod p, 1 integer product (16-bit limbs)
+  uint64_t p;
+  const void* a;
+  size_t la;
+  const void* b;
+  size_t lb;
+  void* c;
+  size_t esz() const { return kind == 1 ? 2 : (p < (1ull << 31) ? 4 : 8); }
+  size_t out_elems() const { return kind == 1 ? (la + lb + 1) / 2 : la + lb - 1; }
+  size_t out_esz() const { return kind == 1 ? 4 : esz(); }
+  size_t op_bytes() const { return up(la * esz()) + up(lb * esz()); }
+  size_t out_bytes() const { return up(out_elems() * out_esz()); }
+};
+
+// First-fit allocator over [0, size) with coalescing.
+struct Arena {
+  std::map<size_t, size_t> free_;  // offset -> size
+  size_t used = 0;
+  explicit Arena(size_t size) { free_[0] = size; }
+  bool alloc(size_t n, size_t* off) {
+    n = up(std::max<size_t>(n, 1));
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < n) continue;
+      *off = it->first;
+      const size_t rest = it->second - n;
+      const size_t o = it->first;
+      free_.erase(it);
+      if (rest) free_[o + n] = rest;
+      used += n;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = up(std::max<size_t>(n, 1));
+    used -= n;
+    auto it = free_.emplace(off, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+// Host copies split into pieces that the pool's threads and the calling thread take in
+// turn; copy() returns when every piece is done.
+class CopyPool {
+ public:
+  struct Copy {
+    void* dst;
+    const void* src;
+    size_t n;
+  };
+  explicit CopyPool(int threads) {
+    for (int i = 0; i < threads; ++i) th_.emplace_back([this] { worker(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  void copy(const std::vector<Copy>& jobs) {
+    static const size_t kPiece = 1u << 20;
+    auto w = std::make_shared<Work>();
+    size_t total = 0;
+    for (const Copy& c : jobs) {
+      total += c.n;
+      for (size_t o = 0; o < c.n; o += kPiece)
+        w->p.push_back(Copy{(char*)c.dst + o, (const char*)c.src + o, std::min(kPiece, c.n - o)});
+    }
+    if (th_.empty() || total < 2 * kPiece) {
+      for (const Copy& c : jobs) memcpy(c.dst, c.src, c.n);
+      return;
+    }
+    w->left = w->p.size();
+    {
+      std::lock_guard<std::mutex> g(m_);
+      cur_ = w;
+      ++gen_;
+    }
+    cv_.notify_all();
+    run(*w);
+    std::unique_lock<std::mutex> lk(w->m);
+    w->cv.wait(lk, [&] { return w->left.load() == 0; });
+  }
+
+ private:
+  struct Work {
+    std::vector<Copy> p;
+    std::atomic<size_t> next{0}, left{0};
+    std::mutex m;
+    std::condition_variable cv;
+  };
+  static void run(Work& w) {
+    for (;;) {
+      const size_t i = w.next.fetch_add(1);
+      if (i >= w.p.size()) return;
+      memcpy(w.p[i].dst, w.p[i].src, w.p[i].n);
+      if (w.left.fetch_sub(1) == 1) {
+        std::lock_guard<std::mutex> g(w.m);
+        w.cv.notify_all();
+      }
+    }
+  }
+  void worker() {
+    uint64_t seen = 0;
+    for (;;) {
+      std::shared_ptr<Work> w;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        w = cur_;
+      }
+      run(*w);
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_;
+  std::shared_ptr<Work> cur_;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+struct Staging {
+  void* host = nullptr;
+  size_t cap = 0;
+  bool busy = false;
+};
+
+struct Batch {
+  std::vector<Req> reqs;
+  std::vector<size_t> off_a, off_b, off_c;  // offsets inside the block (and staging)
+  size_t op_bytes = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0, block = 0, block_bytes = 0;
+  int staging = -1;
+  hipEvent_t ev = nullptr;
+};
+
+}  // namespace
+
+struct ntt_server {
+  int device = 0;
+  unsigned char* dbuf = nullptr;
+  size_t budget = 0;
+  Arena* arena = nullptr;
+  std::vector<hipStream_t> streams;
+  unsigned next_stream = 0;
+  size_t max_batch = 64;
+  size_t staging_cap = 128u << 20;  // operand + product bytes of one polynomial batch
+  std::vector<Staging> staging;
+  std::vector<hipEvent_t> free_events;
+  std::deque<Req> pending;
+  std::deque<Batch> inflight;
+  size_t max_inflight = 0;
+  size_t inflight_cap = 8;  // batches in flight at once: 2 per stream, one staging block each
+  CopyPool* pool = nullptr;
+};
+
+namespace {
+
+int acquire_staging(ntt_server* s, size_t bytes, int* idx) {
+  for (size_t i = 0; i < s->staging.size(); ++i) {
+    if (!s->staging[i].busy && s->staging[i].cap >= bytes) {
+      s->staging[i].busy = true;
+      *idx = (int)i;
+      return NTT_OK;
+    }
+  }
+  Staging st;
+  st.cap = std::max(bytes, s->staging_cap);
+  if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess) return NTT_ENOMEM;
+  st.busy = true;
+  s->staging.push_back(st);
+  *idx = (int)s->staging.size() - 1;
+  return NTT_OK;
+}
+
+// Layout of a batch and its device bytes (operands, products, library workspace).
+int layout(Batch& bt) {
+  size_t o = 0;
+  bt.off_a.clear();
+  bt.off_b.clear();
+  bt.off_c.clear();
+  for (const Req& r : bt.reqs) {
+    bt.off_a.push_back(o);
+    o += up(r.la * r.esz());
+    bt.off_b.push_back(o);
+    o += up(r.lb * r.esz());
+  }
+  bt.op_bytes = o;
+  for (const Req& r : bt.reqs) {
+    bt.off_c.push_back(o);
+    o += r.out_bytes();
+  }
+  bt.out_bytes = o - bt.op_bytes;
+  bt.ws_off = o;
+  if (bt.reqs[0].kind == 1) {
+    bt.ws_bytes = intmul_workspace_bytes(bt.reqs[0].la, bt.reqs[0].lb);
+  } else {
+    std::vector<ntt_polymul_desc> d(bt.reqs.size());
+    for (size_t i = 0; i < bt.reqs.size(); ++i) {
+      const Req& r = bt.reqs[i];
+      // shapes only: any aligned pointers
+      d[i] = ntt_polymul_desc{r.p, (const void*)(uintptr_t)4096, r.la, (const void*)(uintptr_t)4096, r.lb,
+                              (void*)(uintptr_t)4096};
+    }
+    bt.ws_bytes = polymul_batch_workspace_bytes(d.data(), d.size());
+  }
+  bt.block_bytes = bt.ws_off + up(bt.ws_bytes);
+  return NTT_OK;
+}
+
+int launch(ntt_server* s, Batch& bt) {
+  int rc = acquire_staging(s, bt.op_bytes + bt.out_bytes, &bt.staging);
+  if (rc) return rc;
+  unsigned char* host = (unsigned char*)s->staging[bt.staging].host;
+  std::vector<CopyPool::Copy> cp;
+  for (size_t i = 0; i < bt.reqs.size(); ++i) {
+    const Req& r = bt.reqs[i];
+    cp.push_back(CopyPool::Copy{host + bt.off_a[i], r.a, r.la * r.esz()});
+    cp.push_back(CopyPool::Copy{host + bt.off_b[i], r.b, r.lb * r.esz()});
+  }
+  s->pool->copy(cp);
+  hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
+  unsigned char* dev = s->dbuf + bt.block;
+  if (hipMemcpyAsync(dev, host, bt.op_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return NTT_EDEVICE;
+  if (bt.reqs[0].kind == 1) {
+    const Req& r = bt.reqs[0];
+    rc = intmul_crt((const uint16_t*)(dev + bt.off_a[0]), r.la, (const uint16_t*)(dev + bt.off_b[0]), r.lb,
+                    (uint32_t*)(dev + bt.off_c[0]), dev + bt.ws_off, bt.ws_bytes, st);
+  } else {
+    std::vector<ntt_polymul_desc> d(bt.reqs.size());
+    for (size_t i = 0; i < bt.reqs.size(); ++i) {
+      const Req& r = bt.reqs[i];
+      d[i] = ntt_polymul_desc{r.p, dev + bt.off_a[i], r.la, dev + bt.off_b[i], r.lb, dev + bt.off_c[i]};
+    }
+    rc = polymul_modp_batch(d.data(), d.size(), bt.ws_bytes ? dev + bt.ws_off : nullptr, bt.ws_bytes, st);
+  }
+  if (rc) return rc;
+  bool want = false;
+  for (const Req& r : bt.reqs) want |= r.c != nullptr;
+  if (want && hipMemcpyAsync(host + bt.op_bytes, dev + bt.op_bytes, bt.out_bytes, hipMemcpyDeviceToHost, st) !=
+                  hipSuccess)
+    return NTT_EDEVICE;
+  if (!s->free_events.empty()) {
+    bt.ev = s->free_events.back();
+    s->free_events.pop_back();
+  } else if (hipEventCreateWithFlags(&bt.ev, hipEventDisableTiming) != hipSuccess) {
+    return NTT_EDEVICE;
+  }
+  if (hipEventRecord(bt.ev, st) != hipSuccess) return NTT_EDEVICE;
+  return NTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t max_batch) {
+  if (!out || hbm_budget == 0 || streams < 1 || streams > 16 || max_batch < 1) return NTT_EINVAL;
+  *out = nullptr;
+  ntt_server* s = new (std::nothrow) ntt_server();
+  if (!s) return NTT_ENOMEM;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return NTT_EDEVICE;
+  }
+  if (hipMalloc((void**)&s->dbuf, hbm_budget) != hipSuccess) {
+    delete s;
+    return NTT_ENOMEM;
+  }
+  s->budget = hbm_budget;
+  s->arena = new Arena(hbm_budget);
+  {
+    const unsigned hw = std::thread::hardware_concurrency();
+    s->pool = new CopyPool((int)std::min(7u, hw > 1 ? hw - 1 : 0u));  // plus the calling thread
+  }
+  s->max_batch = max_batch;
+  for (int i = 0; i < streams; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {  // default priority
+      ntt_server_destroy(s);
+      return NTT_EDEVICE;
+    }
+    s->streams.push_back(st);
+  }
+  // page-locked staging allocated once (its allocation is slow), one block per batch in flight
+  s->inflight_cap = 2 * (size_t)streams;
+  for (size_t i = 0; i < s->inflight_cap; ++i) {
+    Staging st;
+    st.cap = s->staging_cap;
+    if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess) {
+      ntt_server_destroy(s);
+      return NTT_ENOMEM;
+    }
+    s->staging.push_back(st);
+  }
+  *out = s;
+  return NTT_OK;
+}
+
+int ntt_server_destroy(ntt_server* s) {
+  if (!s) return NTT_OK;
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  for (Batch& b : s->inflight)
+    if (b.ev) (void)hipEventDestroy(b.ev);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
+  for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+  for (Staging& st : s->staging)
+    if (st.host) (void)hipHostFree(st.host);
+  if (s->dbuf) (void)hipFree(s->dbuf);
+  delete s->pool;
+  delete s->arena;
+  delete s;
+  return NTT_OK;
+}
+
+int ntt_server_submit(ntt_server* s, uint64_t id, int kind, uint64_t p, const void* a, size_t la, const void* b,
+                      size_t lb, void* c) {
+  if (!s || !a || !b || la == 0 || lb == 0 || (kind != 0 && kind != 1)) return NTT_EINVAL;
+  if (kind == 0) {
+    if (p < 3 || p >= (1ull << 62) || !ntt_is_prime(p)) return NTT_ENOTPRIME;
+    int L = 0;
+    while (((size_t)1 << L) < la + lb - 1) ++L;
+    if (((p - 1) & (((uint64_t)1 << L) - 1)) != 0 || L > 26) return NTT_ENOROOT;
+  } else if (la + lb - 1 > ((size_t)1 << 23)) {
+    return NTT_EINVAL;
+  }
+  Req r{id, kind, p, a, la, b, lb, c};
+  Batch one;
+  one.reqs.push_back(r);
+  layout(one);
+  if (one.block_bytes > s->budget) return NTT_ENOMEM;  // never fits, even alone
+  s->pending.push_back(r);
+  return NTT_OK;
+}
+
+int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* ndone) {
+  if (!s || !ndone || (cap && !done_ids)) return NTT_EINVAL;
+  *ndone = 0;
+  // completions, in launch order per stream; a finished batch frees its memory
+  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+    if (*ndone + it->reqs.size() > cap) break;
+    const hipError_t q = hipEventQuery(it->ev);
+    if (q == hipErrorNotReady) {
+      ++it;
+      continue;
+    }
+    if (q != hipSuccess) return NTT_EDEVICE;
+    const unsigned char* host = (const unsigned char*)s->staging[it->staging].host;
+    std::vector<CopyPool::Copy> cp;
+    for (size_t i = 0; i < it->reqs.size(); ++i) {
+      const Req& r = it->reqs[i];
+      if (r.c) cp.push_back(CopyPool::Copy{r.c, host + it->off_c[i], r.out_elems() * r.out_esz()});
+      done_ids[(*ndone)++] = r.id;
+    }
+    s->pool->copy(cp);
+    s->staging[it->staging].busy = false;
+    s->arena->release(it->block, it->block_bytes);
+    s->free_events.push_back(it->ev);
+    it = s->inflight.erase(it);
+  }
+  // admissions in arrival order
+  while (!s->pending.empty() && s->inflight.size() < s->inflight_cap) {
+    Batch bt;
+    if (s->pending.front().kind == 1) {
+      bt.reqs.push_back(s->pending.front());
+    } else {
+      size_t staged = 0;
+      for (const Req& r : s->pending) {
+        if (r.kind != 0 || bt.reqs.size() >= s->max_batch) break;
+        const size_t nb = r.op_bytes() + r.out_bytes();
+        if (!bt.reqs.empty() && staged + nb > s->staging_cap) break;
+        bt.reqs.push_back(r);
+        staged += nb;
+      }
+    }
+    // shrink the batch until its block fits in the arena
+    bool placed = false;
+    while (!bt.reqs.empty()) {
+      layout(bt);
+      if (s->arena->alloc(bt.block_bytes, &bt.block)) {
+        placed = true;
+        break;
+      }
+      bt.reqs.pop_back();
+    }
+    if (!placed) break;  // wait for memory to free up
+    for (size_t i = 0; i < bt.reqs.size(); ++i) s->pending.pop_front();
+    int rc = launch(s, bt);
+    if (rc) return rc;
+    s->inflight.push_back(bt);
+    s->max_inflight = std::max(s->max_inflight, s->inflight.size());
+  }
+  return NTT_OK;
+}
+
+int ntt_server_stats(const ntt_server* s, size_t* pending, size_t* inflight, size_t* arena_used, size_t* max_inflight) {
+  if (!s) return NTT_EINVAL;
+  if (pending) *pending = s->pending.size();
+  if (inflight) *inflight = s->inflight.size();
+  if (arena_used) *arena_used = s->arena->used;
+  if (max_inflight) *max_inflight = s->max_inflight;
+  return NTT_OK;
+}
+
+}  // extern "C"

@@ -46,6 +46,7 @@ EXPORTS = (
     "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
+    "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
 )
 
 
@@ -112,6 +113,11 @@ def load(path: str = LIB_PATH):
         "ntt_tune_clear": (ci, []),
         "ntt_tune_load": (ci, [ctypes.c_char_p]),
         "ntt_plan_cache_clear": (ci, []),
+        "ntt_server_create": (ci, [ctypes.POINTER(vp), sz, ci, sz]),
+        "ntt_server_submit": (ci, [vp, u64, ci, u64, vp, sz, vp, sz, vp]),
+        "ntt_server_progress": (ci, [vp, ctypes.POINTER(u64), sz, ctypes.POINTER(sz)]),
+        "ntt_server_stats": (ci, [vp, ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz), ctypes.POINTER(sz)]),
+        "ntt_server_destroy": (ci, [vp]),
         "ntt_graph_begin": (ci, [vp]),
         "ntt_graph_end": (ci, [vp, ctypes.POINTER(vp)]),
         "ntt_graph_launch": (ci, [vp, vp]),

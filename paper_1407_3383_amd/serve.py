@@ -16,6 +16,7 @@ Everything numeric runs in the HIP library; this module only schedules.
 from __future__ import annotations
 
 import collections
+import ctypes
 import time
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -301,6 +302,88 @@ class Server:
                 time.sleep(max(0.0, min(reqs[i].arrival - now_fn(), 0.001)))
         self.torch.cuda.synchronize()
         return now_fn()
+
+
+class NativeServer:
+    """The same request loop in the library (ntt_server_*): admission, batching, staging
+    and completion run in native code; this class only feeds arrivals and collects
+    completions.  Results always come back to host arrays (Request.result)."""
+
+    def __init__(self, budget_bytes: int, streams: int = 4, max_batch: int = 64, keep_results: bool = True):
+        import torch
+        self.torch = torch
+        L = ntt.load()
+        h = ctypes.c_void_p()
+        ntt._check(L.ntt_server_create(ctypes.byref(h), budget_bytes, streams, max_batch), "ntt_server_create")
+        self.h = h
+        self.budget = budget_bytes
+        self.keep_results = keep_results
+        self.completed: List[Request] = []
+        self.max_inflight_batches = 0
+
+    def stats(self):
+        L = ntt.load()
+        v = [ctypes.c_size_t() for _ in range(4)]
+        ntt._check(L.ntt_server_stats(self.h, *[ctypes.byref(x) for x in v]), "ntt_server_stats")
+        return {"pending": v[0].value, "inflight": v[1].value, "arena_used": v[2].value,
+                "max_inflight": v[3].value}
+
+    def run(self, requests: List[Request], realtime: bool = True):
+        """Serve `requests` (sorted by arrival); returns wall seconds of the run."""
+        L = ntt.load()
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        byid = {}
+        for r in reqs:
+            n = (r.a.size + r.b.size + 1) // 2 if r.kind == "int" else r.a.size + r.b.size - 1
+            dt = np.uint32 if (r.kind == "int" or r.p < (1 << 31)) else np.uint64
+            # result buffers touched before the run, so that no page is first touched
+            # by the copy-back inside it
+            r.result = np.zeros(n, dtype=dt) if self.keep_results else None
+            if r.result is not None:
+                r.result.fill(1)
+            r.a = np.ascontiguousarray(r.a)
+            r.b = np.ascontiguousarray(r.b)
+            r.bfly = butterflies(r.a.size, r.b.size, 3 if r.kind == "int" else 1)
+            byid[r.rid] = r
+        cap = 4096
+        ids = (ctypes.c_uint64 * cap)()
+        nd = ctypes.c_size_t()
+        t0 = time.perf_counter()
+        i, total, done = 0, len(reqs), 0
+        while done < total:
+            now = time.perf_counter() - t0
+            while i < total and (not realtime or reqs[i].arrival <= now):
+                r = reqs[i]
+                rc = L.ntt_server_submit(self.h, r.rid, 1 if r.kind == "int" else 0, r.p,
+                                         r.a.ctypes.data, r.a.size, r.b.ctypes.data, r.b.size,
+                                         r.result.ctypes.data if r.result is not None else None)
+                if rc != ntt.NTT_OK:
+                    raise ValueError("request %d refused by the server (%d)" % (r.rid, rc))
+                r.admitted = now
+                i += 1
+            ntt._check(L.ntt_server_progress(self.h, ids, cap, ctypes.byref(nd)), "ntt_server_progress")
+            if nd.value:
+                t = time.perf_counter() - t0
+                for k in range(nd.value):
+                    r = byid[ids[k]]
+                    r.done = t
+                    self.completed.append(r)
+                done += nd.value
+            elif i < total and realtime and done == i:
+                time.sleep(max(0.0, min(reqs[i].arrival - (time.perf_counter() - t0), 0.0005)))
+        self.max_inflight_batches = self.stats()["max_inflight"]
+        return time.perf_counter() - t0
+
+    def close(self):
+        if getattr(self, "h", None):
+            ntt.load().ntt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def latency_stats(done: List[Request]):

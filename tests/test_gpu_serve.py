@@ -101,3 +101,47 @@ def test_serve_mixes_integer_and_polynomial_requests():
     for r in polys:
         assert_equal_u(r.result, _alone(r), "request %d mix vs alone" % r.rid)
     assert srv.arena.used == 0
+
+
+# ---------------------------------------------------------------- native request loop
+
+def test_native_server_mix_equals_alone_and_oracle():
+    torch_cuda()
+    polys = _requests(50, rate=30000.0, lo=8.0, hi=15.0, seed=5)
+    ints = []
+    for k in range(8):
+        n = 200 + 3000 * k
+        a = inputs.limbs16(n, inputs.CFG_SERVE, 7000 + k, 0)
+        b = inputs.limbs16(n // 2 + 1, inputs.CFG_SERVE, 7000 + k, 1)
+        ints.append(serve.Request(80000 + k, 0, a, b, arrival=float(polys[3 * k].arrival), kind="int"))
+    reqs = polys + ints
+    srv = serve.NativeServer(budget_bytes=256 << 20, streams=4, max_batch=16)
+    say("native server: %d polynomial and %d integer products" % (len(polys), len(ints)))
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    st = srv.stats()
+    assert st["pending"] == 0 and st["inflight"] == 0 and st["arena_used"] == 0
+    assert st["max_inflight"] >= 2, "no batches overlapped on the device"
+    for r in polys:
+        assert_equal_u(r.result, _alone(r), "native request %d mix vs alone" % r.rid)
+    for r in polys[:10]:
+        assert_equal_u(r.result, oracle.polymul_ntt(r.a, r.b, r.p), "native request %d vs oracle" % r.rid)
+    for r in ints:
+        assert_equal_u(r.result, oracle.intmul_pyint(r.a, r.b), "native integer request %d vs Python int" % r.rid)
+    srv.close()
+
+
+def test_native_server_small_budget_and_refusal():
+    torch_cuda()
+    reqs = _requests(20, rate=1e6, lo=10.0, hi=13.0, seed=6)
+    biggest = max(serve.footprint(r.p, r.a.size, r.b.size) for r in reqs)
+    srv = serve.NativeServer(budget_bytes=biggest + (1 << 20), streams=2, max_batch=8)
+    srv.run(reqs)
+    assert len(srv.completed) == len(reqs)
+    for r in reqs:
+        assert_equal_u(r.result, _alone(r), "native request %d under a small budget" % r.rid)
+    srv.close()
+    tiny = serve.NativeServer(budget_bytes=4096)
+    with pytest.raises(ValueError):
+        tiny.run(_requests(2, rate=1000.0, lo=14.0, hi=14.5, seed=7))
+    tiny.close()
