@@ -95,9 +95,9 @@ def main() -> int:
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "serve", "all"],
+                    choices=["batch", "polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "serve", "all"],
                     help="batch (default, the headline line) or one of the other configurations")
-    ap.add_argument("--serve-requests", type=int, default=600)
+    ap.add_argument("--serve-requests", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -121,7 +121,7 @@ def main() -> int:
         return 0
     if args.workload != "batch":
         import bench_workloads
-        names = (["polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "serve"] if args.workload == "all"
+        names = (["polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "serve"] if args.workload == "all"
                  else [args.workload])
         for name in names:
             print(json.dumps(bench_workloads.run(name, args)), flush=True)

@@ -288,6 +288,24 @@ size_t intmul32_workspace_bytes(size_t na, size_t nb);
 int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uint32_t* c, void* workspace,
                  size_t ws_bytes, void* hip_stream);
 
+/* Polynomial matrix product (section 5.2): C = A B for n x n matrices over F_p[x]
+ * whose entries have degree < d, through transforms of length N = 2^ceil(log2(2d - 1))
+ * of every entry, one n x n matrix product over F_p per frequency, and the inverse
+ * transforms of C's entries.
+ * A, B: device, n*n*d canonical residues (uint32) each; entry (i, j) holds its d
+ *   coefficients, lowest degree first, at offset (i*n + j)*d.
+ * C: device, n*n*(2d - 1) canonical residues; entry (i, j) at (i*n + j)*(2d - 1).
+ * p: prime below 2^31 with 2^ceil(log2(2d - 1)) dividing p - 1.  1 <= n <= 64.
+ * workspace: device, polymatmul_workspace_bytes(p, n, d) bytes (2 n^2 N words),
+ *   256-byte aligned, owned by the caller.  Asynchronous on hip_stream.
+ * n == 0 or d == 0: nothing to do, NTT_OK.
+ * Errors: NTT_ENOTPRIME, NTT_ENOROOT, NTT_EUNSUPPORTED (p >= 2^31, n > 64),
+ *   NTT_EINVAL (NULL or misaligned pointers, d > 2^25), NTT_ENOMEM (workspace too small),
+ *   NTT_EDEVICE (launch failure). */
+size_t polymatmul_workspace_bytes(uint64_t p, size_t n, size_t d);
+int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
+                    size_t ws_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

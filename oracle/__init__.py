@@ -11,7 +11,8 @@ Contents
 * ``ntt_oracle.c`` (built into ``libntt_oracle.so`` with gcc): the plain definitions
   in C with unsigned __int128 products and ``%`` reductions -- DFT by definition,
   Horner evaluation, a textbook radix-2 transform, schoolbook and transform-based
-  polynomial products, schoolbook and three-prime integer products, Garner digits.
+  polynomial products, the schoolbook polynomial matrix product, schoolbook and
+  three-prime integer products, Garner digits.
 * ``numtheory``: primality (deterministic Miller-Rabin), primitive roots, roots of
   unity, the rule that picks the ~62-bit prime, Barrett / Shoup / Montgomery
   constants by their definitions -- in Python integers.
@@ -71,6 +72,8 @@ def lib():
             "orc_mulmod_vec": (None, [u64, vp, vp, vp, sz]),
             "orc_limbs32_mod": (u64, [vp, sz, u64]),
             "orc_limbs16_mod": (u64, [vp, sz, u64]),
+            "orc_polymatmul": (None, [u64, sz, vp, vp, sz, vp]),
+            "orc_polymatmul_coeff": (u64, [u64, sz, vp, vp, sz, sz, sz, sz]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -188,6 +191,30 @@ def polymul_ntt(a, b, p: int, g: int | None = None) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("orc_polymul_ntt failed: %d" % rc)
     return c
+
+
+def _matrix_operands(A, B):
+    x, y = np.asarray(A), np.asarray(B)
+    if x.ndim != 3 or x.shape != y.shape or x.shape[0] != x.shape[1]:
+        raise ValueError("A and B must both have shape (n, n, d)")
+    return _u64(x.reshape(-1)), _u64(y.reshape(-1)), x.shape[0], x.shape[2]
+
+
+def polymatmul(A, B, p: int) -> np.ndarray:
+    """Polynomial matrix product (section 5.2): A, B of shape (n, n, d) over F_p,
+    C[i, j] = sum_l A[i, l] * B[l, j] as polynomials, shape (n, n, 2d - 1)."""
+    x, y, n, d = _matrix_operands(A, B)
+    if n == 0 or d == 0:
+        return np.zeros((n, n, max(2 * d - 1, 0)), dtype=np.uint64)
+    c = np.empty(n * n * (2 * d - 1), dtype=np.uint64)
+    lib().orc_polymatmul(p, n, _ptr(x), _ptr(y), d, _ptr(c))
+    return c.reshape(n, n, 2 * d - 1)
+
+
+def polymatmul_coeff(A, B, p: int, i: int, j: int, k: int) -> int:
+    """One coefficient C[i, j][k] of the polynomial matrix product, O(n d)."""
+    x, y, n, d = _matrix_operands(A, B)
+    return int(lib().orc_polymatmul_coeff(p, n, _ptr(x), _ptr(y), d, i, j, k))
 
 
 INTMUL_PRIMES = (998244353, 469762049, 167772161)

@@ -266,6 +266,37 @@ void orc_mulmod_vec(uint64_t p, const uint64_t* a, const uint64_t* b, uint64_t* 
   for (size_t i = 0; i < n; ++i) out[i] = orc_mulmod(a[i], b[i], p);
 }
 
+/*
+ * Polynomial matrix product (section 5.2): C = A B for n x n matrices over F_p[x]
+ * whose entries have degree < d.  Entry (i, j) of C is sum_l A_il B_lj, the products
+ * of polynomials written out coefficient by coefficient:
+ *   C_ij[k] = sum_l sum_{s + t = k} A_il[s] B_lj[t]  mod p,  k < 2d - 1.
+ * Layout: entry (i, j) of A and B at (i n + j) d, of C at (i n + j)(2d - 1).
+ */
+uint64_t orc_polymatmul_coeff(uint64_t p, size_t n, const uint64_t* A, const uint64_t* B, size_t d, size_t i,
+                              size_t j, size_t k) {
+  u128 acc = 0;
+  const size_t s0 = k >= d ? k - (d - 1) : 0;
+  const size_t s1 = k < d ? k : d - 1;
+  for (size_t l = 0; l < n; ++l) {
+    const uint64_t* a = A + (i * n + l) * d;
+    const uint64_t* b = B + (l * n + j) * d;
+    for (size_t s = s0; s <= s1; ++s) {
+      acc += (u128)orc_mulmod(a[s], b[k - s], p);
+      if (acc >> 120) acc %= p;
+    }
+  }
+  return (uint64_t)(acc % p);
+}
+
+void orc_polymatmul(uint64_t p, size_t n, const uint64_t* A, const uint64_t* B, size_t d, uint64_t* C) {
+  if (n == 0 || d == 0) return;
+  const size_t lc = 2 * d - 1;
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = 0; j < n; ++j)
+      for (size_t k = 0; k < lc; ++k) C[(i * n + j) * lc + k] = orc_polymatmul_coeff(p, n, A, B, d, i, j, k);
+}
+
 void orc_horner_many(uint64_t p, const uint64_t* a, size_t n, const uint64_t* xs, uint64_t* out, size_t m) {
   for (size_t i = 0; i < m; ++i) out[i] = orc_horner(p, a, n, xs[i]);
 }

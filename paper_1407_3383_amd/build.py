@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libntt_mi355x.so")
-SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip"]
+SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip",
+           "kernels_matrix.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -1720,3 +1720,165 @@ int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uin
 
 }  // extern "C"
 
+// ============================================================================ polynomial matrices
+namespace {
+
+// Transform length of the polynomial matrix product: N = 2^L >= 2d - 1.
+int polymat_log2(size_t d) {
+  const size_t lc = 2 * d - 1;
+  int L = 0;
+  while (((size_t)1 << L) < lc) ++L;
+  return L;
+}
+
+int polymat_check(uint64_t p, size_t n, size_t d) {
+  if (n == 0 || d == 0) return NTT_OK;
+  if (p < 3 || !is_prime_u64(p)) return fail(NTT_ENOTPRIME, "%llu is not an odd prime", (unsigned long long)p);
+  if (p >= (1ull << 31)) return fail(NTT_EUNSUPPORTED, "the matrix product takes primes below 2^31");
+  if (n > kMatMaxN) return fail(NTT_EUNSUPPORTED, "n = %zu exceeds %u", n, kMatMaxN);
+  if (d > ((size_t)1 << 25)) return fail(NTT_EINVAL, "degree bound d = %zu too large", d);
+  const int L = polymat_log2(d);
+  if (((p - 1) & (((uint64_t)1 << L) - 1)) != 0)
+    return fail(NTT_ENOROOT, "2^%d does not divide p - 1 = %llu", L, (unsigned long long)(p - 1));
+  return NTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t polymatmul_workspace_bytes(uint64_t p, size_t n, size_t d) {
+  if (n == 0 || d == 0 || polymat_check(p, n, d)) return 0;
+  const size_t N = (size_t)1 << polymat_log2(d);
+  return 2 * align256(n * n * N * sizeof(uint32_t));
+}
+
+int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
+                    size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (n == 0 || d == 0) return ok();
+    if (!A || !B || !C) return fail(NTT_EINVAL, "NULL matrix pointer");
+    if (!aligned_to(A, 4) || !aligned_to(B, 4) || !aligned_to(C, 4)) return fail(NTT_EINVAL, "misaligned pointer");
+    int rc = polymat_check(p, n, d);
+    if (rc) return rc;
+    const int L = polymat_log2(d);
+    const size_t N = (size_t)1 << L, lc = 2 * d - 1, n2 = n * n;
+    const size_t need = polymatmul_workspace_bytes(p, n, d);
+    if (ws_bytes < need || !workspace) return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    ntt_plan* pl = nullptr;
+    rc = cached_plan(p, (uint32_t)L, &pl);
+    if (rc) return rc;
+    uint32_t* Ah = (uint32_t*)workspace;
+    uint32_t* Bh = (uint32_t*)((unsigned char*)workspace + align256(n2 * N * sizeof(uint32_t)));
+    const bool two_pass = pl->passes > 1;
+    // forward transforms of the 2 n^2 entries, zero-padded from d to N, TFT order
+    PassArgs x;
+    memset(&x, 0, sizeof(x));
+    if (two_pass) {
+      x.pc = pl->passc;
+      x.tw = pl->tw;
+      x.twi = pl->twi;
+      x.tlo = pl->tlo;
+      x.thi = pl->thi;
+      x.tilo = pl->tilo;
+      x.tihi = pl->tihi;  // no 1/N in the inverse: K carries it
+      x.batch = (uint32_t)n2;
+      x.in_stride = d;
+      x.out_stride = N;
+      x.valid = d;
+      PassJobs fwd;
+      memset(&fwd, 0, sizeof(fwd));
+      x.in = A;
+      x.out = Ah;
+      fwd.j[fwd.n++] = x;
+      x.in = B;
+      x.out = Bh;
+      fwd.j[fwd.n++] = x;
+      HIP_TRY(launch_col_fwd_jobs(32, fwd, (int)pl->L1, (int)pl->L2, stream));
+      PassArgs r = x;
+      r.in_stride = N;
+      r.valid = N;
+      r.in = Ah;
+      r.out = Ah;
+      HIP_TRY(launch_row_fwd(32, r, (int)pl->L1, (int)pl->L2, stream));
+      r.in = Bh;
+      r.out = Bh;
+      HIP_TRY(launch_row_fwd(32, r, (int)pl->L1, (int)pl->L2, stream));
+    } else {
+      HIP_TRY(launch_copy_rows(Ah, N, N, (const uint32_t*)A, d, d, (uint32_t)n2, stream));
+      HIP_TRY(launch_copy_rows(Bh, N, N, (const uint32_t*)B, d, d, (uint32_t)n2, stream));
+      LdsNttArgs t;
+      memset(&t, 0, sizeof(t));
+      t.in = Ah;
+      t.out = Ah;
+      t.stride = N;
+      t.pc = pl->passc;
+      t.tw = pl->tw;
+      t.twi = pl->twi;
+      t.L = (uint32_t)L;
+      t.bitrev = 1;
+      t.batch = (uint32_t)n2;
+      HIP_TRY(launch_lds_ntt(32, false, t, stream));
+      t.in = Bh;
+      t.out = Bh;
+      HIP_TRY(launch_lds_ntt(32, false, t, stream));
+    }
+    // n x n products at every frequency, written over A's transforms
+    MatArgs m;
+    memset(&m, 0, sizeof(m));
+    m.A = Ah;
+    m.B = Bh;
+    m.C = Ah;
+    m.N = N;
+    m.n = (uint32_t)n;
+    m.kb = freq_matmul_block((uint32_t)n, N);
+    m.p = (uint32_t)p;
+    uint32_t inv = (uint32_t)p;  // p^-1 mod 2^32 by Newton's iteration
+    for (int i = 0; i < 5; ++i) inv *= 2u - (uint32_t)p * inv;
+    m.pinv = inv;
+    const uint64_t r32 = (1ull << 32) % p;
+    m.r32 = (uint32_t)r32;
+    const u128 room = ((u128)1 << 64) - 1 - ((u128)p << 32);
+    const u128 fold = room / ((u128)(p - 1) * (p - 1));
+    m.fold = (uint32_t)std::min<u128>(fold, (u128)n);
+    const uint64_t K = two_pass ? mulmod(r32, pl->ninv, p) : r32;
+    m.kw = (uint32_t)K;
+    m.kws = (uint32_t)((K << 32) / p);
+    HIP_TRY(launch_freq_matmul(m, stream));
+    // inverse transforms of C's n^2 entries, the first 2d - 1 coefficients kept
+    if (two_pass) {
+      PassArgs v = x;
+      v.in = Ah;
+      v.in_stride = N;
+      v.out = Ah;
+      v.out_stride = N;
+      v.valid = N;
+      HIP_TRY(launch_row_inv(32, v, (int)pl->L1, (int)pl->L2, false, stream));
+      v.out = C;
+      v.out_stride = lc;
+      v.valid = lc;
+      HIP_TRY(launch_col_inv(32, v, (int)pl->L1, (int)pl->L2, stream));
+    } else {
+      LdsNttArgs t;
+      memset(&t, 0, sizeof(t));
+      t.in = Ah;
+      t.out = Ah;
+      t.stride = N;
+      t.pc = pl->passc;
+      t.tw = pl->tw;
+      t.twi = pl->twi;
+      t.L = (uint32_t)L;
+      t.bitrev = 1;
+      t.batch = (uint32_t)n2;
+      HIP_TRY(launch_lds_ntt(32, true, t, stream));
+      HIP_TRY(launch_copy_rows((uint32_t*)C, lc, lc, Ah, N, lc, (uint32_t)n2, stream));
+    }
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymatmul_modp");
+  }
+}
+
+}  // extern "C"
+

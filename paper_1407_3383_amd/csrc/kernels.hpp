@@ -134,4 +134,25 @@ hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream);
 hipError_t launch_crt32_carry(const CrtArgs& a, hipStream_t stream);
 hipError_t launch_reduce_mod(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t p, hipStream_t stream);
 
+// Polynomial matrix product, entry-wise step: C[e][k] for every frequency k < N of the
+// n x n matrices whose entries e = i n + j are vectors of N words (A, B: transforms,
+// canonical).  C = (sum_l A[i n + l][k] B[l n + j][k]) 2^-32 K mod p, canonical.
+constexpr uint32_t kMatMaxN = 64;
+struct MatArgs {
+  const uint32_t* A;
+  const uint32_t* B;
+  uint32_t* C;       // may equal A
+  uint64_t N;        // words per entry (a multiple of kb)
+  uint32_t n, kb;    // matrix size; frequencies per workgroup (freq_matmul_block)
+  uint32_t fold;     // products accumulated between folds (>= 1)
+  uint32_t p, pinv;  // p < 2^31, p^-1 mod 2^32
+  uint32_t r32;      // 2^32 mod p
+  uint32_t kw, kws;  // K and floor(K 2^32 / p)
+};
+uint32_t freq_matmul_block(uint32_t n, uint64_t N);
+hipError_t launch_freq_matmul(const MatArgs& a, hipStream_t stream);
+// dst[r][t] = t < src_len ? src[r][t] : 0 for r < rows, t < dst_len.
+hipError_t launch_copy_rows(uint32_t* dst, uint64_t dst_stride, uint64_t dst_len, const uint32_t* src,
+                            uint64_t src_stride, uint64_t src_len, uint32_t rows, hipStream_t stream);
+
 }  // namespace nttgpu

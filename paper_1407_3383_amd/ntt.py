@@ -44,6 +44,7 @@ EXPORTS = (
     "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
+    "polymatmul_workspace_bytes", "polymatmul_modp",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
@@ -108,6 +109,8 @@ def load(path: str = LIB_PATH):
         "intmul_chunk_bits": (ci, [sz, sz]),
         "intmul32_workspace_bytes": (sz, [sz, sz]),
         "intmul_crt32": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
+        "polymatmul_workspace_bytes": (sz, [u64, sz, sz]),
+        "polymatmul_modp": (ci, [u64, sz, vp, vp, sz, vp, vp, sz, vp]),
         "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
         "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
         "ntt_tune_clear": (ci, []),
@@ -376,6 +379,26 @@ def intmul32(a32, b32, out=None, stream=None, workspace=None):
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, a32.device)
     _check(L.intmul_crt32(_ptr(a32), na, _ptr(b32), nb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                           _stream(stream)), "intmul_crt32")
+    return out
+
+
+def polymatmul(A, B, p: int, out=None, stream=None, workspace=None):
+    """Polynomial matrix product (section 5.2): A, B device tensors of shape (n, n, d)
+    holding residues mod p < 2^31 (int32 bit patterns) -> C of shape (n, n, 2d - 1)."""
+    torch = _torch()
+    L = load()
+    if A.dim() != 3 or A.shape != B.shape or A.shape[0] != A.shape[1]:
+        raise ValueError("A and B must both have shape (n, n, d)")
+    n, d = int(A.shape[0]), int(A.shape[2])
+    if not (A.is_contiguous() and B.is_contiguous()):
+        raise ValueError("A and B must be contiguous")
+    lc = max(2 * d - 1, 0)
+    if out is None:
+        out = torch.empty((n, n, lc), dtype=torch.int32, device=A.device)
+    need = L.polymatmul_workspace_bytes(p, n, d)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, A.device)
+    _check(L.polymatmul_modp(p, n, _ptr(A), _ptr(B), d, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                             _stream(stream)), "polymatmul_modp")
     return out
 
 

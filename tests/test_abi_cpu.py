@@ -146,3 +146,23 @@ def test_intmul32_argument_errors_and_sizes(lib):
     assert lib.intmul_crt32(one, 10, one, 10, one, None, 0, None) == ntt.NTT_ENOMEM
     assert lib.intmul_crt32(vp(2), 10, one, 10, one, None, 0, None) == ntt.NTT_EINVAL   # misaligned
     assert lib.intmul32_workspace_bytes(1 << 20, 1 << 20) >= 3 * 4 * ((1 << 21) - 1)
+
+
+def test_polymatmul_argument_errors_and_sizes(lib):
+    vp = ctypes.c_void_p
+    one = vp(16)
+    p = 469762049
+    # Table 15's shape: 32 x 32 matrices, degrees < 2^15, transforms of 2^16 words
+    assert lib.polymatmul_workspace_bytes(p, 32, 1 << 15) == 2 * 32 * 32 * (1 << 16) * 4
+    assert lib.polymatmul_workspace_bytes(p, 0, 10) == 0
+    assert lib.polymatmul_modp(p, 0, one, one, 10, one, None, 0, None) == ntt.NTT_OK
+    assert lib.polymatmul_modp(p, 3, one, one, 0, one, None, 0, None) == ntt.NTT_OK
+    assert lib.polymatmul_modp(p, 3, None, one, 10, one, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.polymatmul_modp(p, 3, vp(18), one, 10, one, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.polymatmul_modp(1000000000, 3, one, one, 10, one, None, 0, None) == ntt.NTT_ENOTPRIME
+    assert lib.polymatmul_modp(4611685941117976577, 3, one, one, 10, one, None, 0, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.polymatmul_modp(p, 65, one, one, 10, one, None, 0, None) == ntt.NTT_EUNSUPPORTED
+    # 7 * 2^20 + 1: degrees < 2^19 + 1 need transforms of 2^21 words
+    assert lib.polymatmul_modp(7340033, 2, one, one, (1 << 19) + 1, one, None, 0, None) == ntt.NTT_ENOROOT
+    assert lib.polymatmul_workspace_bytes(7340033, 2, (1 << 19) + 1) == 0
+    assert lib.polymatmul_modp(p, 3, one, one, 10, one, None, 0, None) == ntt.NTT_ENOMEM
