@@ -98,6 +98,7 @@ def main() -> int:
                     choices=["batch", "polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "serve", "all"],
                     help="batch (default, the headline line) or one of the other configurations")
     ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--matrix-n", type=int, default=0, help="polymatrix: one matrix size only (default 1 .. 32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

@@ -3,12 +3,12 @@
 // C^(k) = A^(k) B^(k); the inverse transforms of C's entries then give C = A B.
 //
 // freq_matmul_kernel: one workgroup owns KB consecutive frequencies.  It stages those
-// frequencies of every entry of A and B in LDS (entry-major, KB words per entry), then
-// each work item -- one frequency and one 4 x 4 tile of C -- accumulates its 16 sums of
-// n products in 64-bit registers (one v_mad_u64_u32 per product).  A tile takes rows
+// frequencies of every entry of A (by rows) and B (by columns) in LDS, then each work
+// item -- one frequency and one 4 x 4 tile of C -- accumulates its 16 sums of n
+// products in 64-bit registers (one v_mad_u64_u32 per product).  A tile takes rows
 // ib + S t and columns jb + S t (S = ceil(n / 4)), so that neighbouring tiles in a wave
-// read neighbouring entries of B (different LDS banks) and the same entries of A (one
-// broadcast).  Every `fold` products the sums are folded, s = hi 2^32 + lo ->
+// read neighbouring columns of B (different LDS banks, by the row padding) and the same
+// row of A (one broadcast).  Every `fold` products the sums are folded, s = hi 2^32 + lo ->
 // hi (2^32 mod p) + lo < p 2^32, which keeps them below 2^64; at the end one Montgomery
 // reduction (Function 13, m = 32) and one product by a constant K (Function 8) give
 // s 2^-32 K mod p: K = 2^32 / N when the inverse transforms do not scale by 1/N, and
@@ -22,28 +22,39 @@ namespace {
 
 constexpr int kMatThreads = 256;
 
+// LDS layout, RS = (n + 1) KB words per matrix row: As[i RS + l KB + kk] = A[i][l] and
+// Bt[j RS + l KB + kk] = B[l][j] at frequency k0 + kk.  Consecutive l are KB words
+// apart in both (immediate offsets once the l loop is unrolled); the KB padding words
+// per row put neighbouring rows of a wave's tiles on different banks.
+template <int KB>
 __global__ __launch_bounds__(kMatThreads) void freq_matmul_kernel(MatArgs M) {
   extern __shared__ __align__(16) uint32_t mat_lds[];
-  const uint32_t n = M.n, KB = M.kb, n2 = n * n;
+  const uint32_t n = M.n, n2 = n * n, RS = (n + 1) * KB;
   const uint64_t N = M.N;
-  const uint64_t k0 = (uint64_t)blockIdx.x * KB;
+  // consecutive frequency slices on one XCD (workgroups are dealt to the 8 XCDs in
+  // turn): the slices of one 128-byte line are then fetched into one L2
+  const uint32_t G = gridDim.x, bid = blockIdx.x;
+  const uint32_t slice = (G & 7u) == 0 ? (bid & 7u) * (G >> 3) + (bid >> 3) : bid;
+  const uint64_t k0 = (uint64_t)slice * KB;
   uint32_t* As = mat_lds;
-  uint32_t* Bs = mat_lds + (size_t)n2 * KB;
+  uint32_t* Bt = mat_lds + (size_t)n * RS;
   const uint32_t tid = threadIdx.x;
-  if (KB >= 4) {
-    const uint32_t q = KB >> 2;
+  if constexpr (KB >= 4) {
+    constexpr uint32_t q = KB / 4;
     for (uint32_t idx = tid; idx < n2 * q; idx += kMatThreads) {
-      const uint32_t e = idx / q, c = (idx - e * q) << 2;
+      const uint32_t e = idx / q, c = (idx - e * q) * 4;
+      const uint32_t r = e / n, s = e - r * n;  // entry (r, s)
       const uint64_t g = (uint64_t)e * N + k0 + c;
-      *(uint4*)(As + (size_t)e * KB + c) = *(const uint4*)(M.A + g);
-      *(uint4*)(Bs + (size_t)e * KB + c) = *(const uint4*)(M.B + g);
+      *(uint4*)(As + r * RS + s * KB + c) = *(const uint4*)(M.A + g);  // A[r][s]: row r, l = s
+      *(uint4*)(Bt + s * RS + r * KB + c) = *(const uint4*)(M.B + g);  // B[r][s]: column s, l = r
     }
   } else {
     for (uint32_t idx = tid; idx < n2 * KB; idx += kMatThreads) {
       const uint32_t e = idx / KB, c = idx - e * KB;
+      const uint32_t r = e / n, s = e - r * n;
       const uint64_t g = (uint64_t)e * N + k0 + c;
-      As[idx] = M.A[g];
-      Bs[idx] = M.B[g];
+      As[r * RS + s * KB + c] = M.A[g];
+      Bt[s * RS + r * KB + c] = M.B[g];
     }
   }
   __syncthreads();
@@ -52,6 +63,14 @@ __global__ __launch_bounds__(kMatThreads) void freq_matmul_kernel(MatArgs M) {
   for (uint32_t w = tid; w < items; w += kMatThreads) {
     const uint32_t t = w / KB, kk = w - t * KB;
     const uint32_t ib = t / S, jb = t - ib * S;
+    // rows ib + S a and columns jb + S b; those beyond n read row / column n - 1 and
+    // are not stored
+    const uint32_t* pa[4];
+    const uint32_t* pb[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) pa[a] = As + min(ib + S * a, n - 1) * RS + kk;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) pb[b] = Bt + min(jb + S * b, n - 1) * RS + kk;
     uint64_t acc[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -59,19 +78,13 @@ __global__ __launch_bounds__(kMatThreads) void freq_matmul_kernel(MatArgs M) {
       for (int b = 0; b < 4; ++b) acc[a][b] = 0;
     for (uint32_t l0 = 0; l0 < n; l0 += M.fold) {
       const uint32_t l1 = min(n, l0 + M.fold);
-#pragma unroll 2
+#pragma unroll 4
       for (uint32_t l = l0; l < l1; ++l) {
         uint32_t x[4], y[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const uint32_t i = ib + S * a;
-          x[a] = i < n ? As[(size_t)(i * n + l) * KB + kk] : 0u;
-        }
+        for (int a = 0; a < 4; ++a) x[a] = pa[a][l * KB];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const uint32_t j = jb + S * b;
-          y[b] = j < n ? Bs[(size_t)(l * n + j) * KB + kk] : 0u;
-        }
+        for (int b = 0; b < 4; ++b) y[b] = pb[b][l * KB];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -119,21 +132,38 @@ __global__ void copy_rows_kernel(uint32_t* dst, uint64_t dst_stride, uint64_t ds
 uint32_t freq_matmul_block(uint32_t n, uint64_t N) {
   if (n == 0 || n > kMatMaxN) return 0;
   uint32_t kb = 256;
-  while (kb > 1 && (uint64_t)n * n * kb > 8192) kb >>= 1;
+  while (kb > 1 && (uint64_t)n * (n + 1) * kb > 8192) kb >>= 1;
   while ((uint64_t)kb > N) kb >>= 1;
   return kb;
+}
+
+template <int KB>
+static hipError_t launch_freq_matmul_kb(const MatArgs& a, hipStream_t stream) {
+  const size_t lds = 2 * (size_t)a.n * (a.n + 1) * KB * sizeof(uint32_t);
+  auto k = freq_matmul_kernel<KB>;
+  hipError_t e = allow_dynamic_lds((const void*)k, lds);
+  if (e != hipSuccess) return e;
+  const uint64_t grid = a.N / KB;
+  if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3((uint32_t)grid), dim3(kMatThreads), lds, stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_freq_matmul(const MatArgs& a, hipStream_t stream) {
   if (a.n == 0 || a.n > kMatMaxN || a.kb == 0 || (a.N % a.kb) != 0 || a.fold == 0) return hipErrorInvalidValue;
   if (a.kb >= 4 && (((uintptr_t)a.A | (uintptr_t)a.B) & 15u)) return hipErrorInvalidValue;
-  const size_t lds = 2 * (size_t)a.n * a.n * a.kb * sizeof(uint32_t);
-  hipError_t e = allow_dynamic_lds((const void*)freq_matmul_kernel, lds);
-  if (e != hipSuccess) return e;
-  const uint64_t grid = a.N / a.kb;
-  if (grid > 0x7FFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(freq_matmul_kernel, dim3((uint32_t)grid), dim3(kMatThreads), lds, stream, a);
-  return hipGetLastError();
+  switch (a.kb) {
+    case 1: return launch_freq_matmul_kb<1>(a, stream);
+    case 2: return launch_freq_matmul_kb<2>(a, stream);
+    case 4: return launch_freq_matmul_kb<4>(a, stream);
+    case 8: return launch_freq_matmul_kb<8>(a, stream);
+    case 16: return launch_freq_matmul_kb<16>(a, stream);
+    case 32: return launch_freq_matmul_kb<32>(a, stream);
+    case 64: return launch_freq_matmul_kb<64>(a, stream);
+    case 128: return launch_freq_matmul_kb<128>(a, stream);
+    case 256: return launch_freq_matmul_kb<256>(a, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_copy_rows(uint32_t* dst, uint64_t dst_stride, uint64_t dst_len, const uint32_t* src,
