@@ -178,6 +178,8 @@ def run(name, args):
                       "note": "untruncated, both batches would take the same time (same transform length)"})
     if name == "polymatrix":
         return run_polymatrix(args)
+    if name == "f64":
+        return run_f64(args)
     if name == "serve":
         return run_serve(args)
     raise ValueError(name)
@@ -326,3 +328,47 @@ def run_serve(args):
     _log("serve with integer products: p50 %.3f ms, p99 %.3f ms" % (st["p50_ms"], st["p99_ms"]))
     torch.cuda.synchronize()
     return out
+
+
+def run_f64(args):
+    """Section 3's numeric-type arithmetic against the 64-bit integer words: 1024
+    products of length-2^14 operands (transform length 2^15, the fused kernel's 64-bit
+    limit) modulo the largest primes below 2^48 and 2^49 with 2^20 | p - 1, and 8192
+    products of length 2^11, once with residues in doubles (Function 16) and once in
+    64-bit integers (Function 8 over 64-bit words), same kernels otherwise."""
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt
+    stream = torch.cuda.Stream()
+    res = {}
+    for bits, items, n in ((48, 1024, 1 << 14), (49, 1024, 1 << 14), (49, 8192, 1 << 11)):
+        N = 2 * n
+        log2N = N.bit_length() - 1
+        bfly = items * 3 * (N // 2) * log2N
+        p = ntt.find_prime(bits, 20)
+        _, A, B = inputs.polymul_batch_inputs(items, n, p)
+        dA, dB = ntt.to_device(A), ntt.to_device(B)
+        C = torch.empty((items, 2 * n - 1), dtype=torch.int64, device="cuda")
+        bt = ntt.Batch.rows(dA, dB, C, p)
+        _, ims = _time(lambda: bt(stream), stream, max(args.steps, 20), 3)
+        Af, Bf = dA.double(), dB.double()
+        Cf = torch.empty((items, 2 * n - 1), dtype=torch.float64, device="cuda")
+        bf = ntt.Batch.rows(Af, Bf, Cf, p, f64=True)
+        _, fms = _time(lambda: bf(stream), stream, max(args.steps, 20), 3)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(Cf.to(torch.int64), C))
+        res["%d-bit p, %d x 2^%d" % (bits, items, log2N - 1)] = {"p": p, "u64_ms": round(ims, 4), "f64_ms": round(fms, 4),
+                     "u64_Gbfly_per_s": round(bfly / (ims * 1e-3) / 1e9, 1),
+                     "f64_Gbfly_per_s": round(bfly / (fms * 1e-3) / 1e9, 1),
+                     "f64_over_u64_speed": round(ims / fms, 3), "identical_results": same}
+        _log("f64 %d-bit prime, %d x 2^%d: u64 %.4f ms, f64 %.4f ms, identical %s"
+             % (bits, items, log2N - 1, ims, fms, same))
+        bt.close()
+        bf.close()
+        del dA, dB, C, Af, Bf, Cf, bt, bf
+    top = res["49-bit p, 1024 x 2^14"]
+    return _line("batched polymul with FP64 residues, 1024 x (2^14 x 2^14) mod a 49-bit prime (Gbutterflies/s)",
+                 top["f64_Gbfly_per_s"], "Gbfly/s", top["f64_ms"], max(args.steps, 20), 3,
+                 {"workload": "1024 products of length-2^14 operands, transform length 2^15, p < 2^49 and p < 2^48"},
+                 {"dtype": "f64", "by_case": res,
+                  "note": "u64: the same batch with 64-bit integer residues (Function 8 over 64-bit words)"})

@@ -306,6 +306,28 @@ size_t polymatmul_workspace_bytes(uint64_t p, size_t n, size_t d);
 int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
                     size_t ws_bytes, void* hip_stream);
 
+/* Products mod p with residues held in doubles (section 3: modular arithmetic over
+ * numeric types; products by Function 16, the FMA product, sums by Function 17's
+ * compare-and-subtract), in the same fused one-workgroup kernels as polymul_modp_batch.
+ * Descriptors as for polymul_modp_batch, except that a, b and c point to device arrays
+ * of double holding canonical residues (integers in [0, p)); c receives la + lb - 1
+ * canonical residues as doubles.
+ * p: prime below 2^49 (operands stay below 2p, or 4p for p < 2^48, between
+ *   butterflies, and Function 16 needs x y < 2^50 p); transform length
+ *   2^ceil(log2(la + lb - 1)) at most 2^15 and dividing p - 1.
+ * workspace: polymul_f64_batch_workspace_bytes(d, count) bytes (the device copy of the
+ *   descriptors).  Asynchronous on hip_stream; not recordable in a graph.
+ * Errors: NTT_EUNSUPPORTED (p >= 2^49, transform longer than 2^15), NTT_ENOTPRIME,
+ *   NTT_ENOROOT, NTT_EINVAL (NULL or misaligned pointers, graph capture), NTT_ENOMEM
+ *   (workspace too small), NTT_EDEVICE. */
+size_t polymul_f64_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
+int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes, void* hip_stream);
+/* The same products as a reusable batch handle (checked, planned and uploaded once):
+ * run with polymul_batch_launch (workspace polymul_batch_launch_workspace_bytes),
+ * freed with polymul_batch_destroy; launches are recordable in a graph.  Errors as
+ * polymul_f64_batch. */
+int polymul_f64_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,6 +39,9 @@ __device__ __forceinline__ uint64_t uni(uint64_t x) {
 }
 __device__ __forceinline__ const void* uni(const void* x) { return (const void*)uni((uint64_t)(uintptr_t)x); }
 __device__ __forceinline__ void* uni(void* x) { return (void*)uni((uint64_t)(uintptr_t)x); }
+__device__ __forceinline__ double uni(double x) {
+  return __longlong_as_double((long long)uni((uint64_t)__double_as_longlong(x)));
+}
 template <typename T>
 __device__ __forceinline__ TwPair<T> uni(const TwPair<T>& t) {
   TwPair<T> r;
@@ -121,6 +124,36 @@ struct Arith<uint64_t> {
     uint64_t m = lo * pinv;
     return hi - __umul64hi(m, p) + p;
   }
+};
+
+// Residues held in doubles (section 3, numeric types: 52 explicit mantissa bits),
+// p < 2^49.  Sums of residues below 2^53 are exact, so the integer butterflies' add,
+// subtract and compare-and-subtract (Function 17) carry over unchanged.  The product
+// is Function 16: h = x y rounded, l = x y - h exactly (one FMA), c = floor(h u) with
+// u = 1/p rounded, d = h - c p exactly (one FMA), e = d + l = x y - c p.  For
+// x y < 2^50 p (Proposition 13 with 52 mantissa bits), c is floor(x y / p) up to one,
+// so e lies in [-p, 2p); one correction gives [0, 2p), the range the integer
+// fixed-multiplicand product leaves.  Operands stay below 4p between butterflies when
+// p < 2^48 (lazy) and below 2p otherwise, so x w < 2^50 p holds for p < 2^49.
+// Explicit _rn operations keep the compiler from contracting h into another FMA.
+template <>
+struct Arith<double> {
+  double p, p2, pinv;  // p, 2p, u = 1/p (rounded to nearest)
+
+  __device__ __forceinline__ double shoup(double x, double w, double) const {
+    const double h = __dmul_rn(x, w);
+    const double l = __fma_rn(x, w, -h);
+    const double c = floor(__dmul_rn(h, pinv));
+    const double d = __fma_rn(-c, p, h);
+    const double e = __dadd_rn(d, l);
+    return e < 0.0 ? __dadd_rn(e, p) : e;
+  }
+  __device__ __forceinline__ double shoup_u(double x, double w, double ws) const { return shoup(x, w, ws); }
+  __device__ __forceinline__ double red1(double x) const { return x >= p ? __dsub_rn(x, p) : x; }
+  __device__ __forceinline__ double red2(double x) const { return x >= p2 ? __dsub_rn(x, p2) : x; }
+  // Product of two residues: the integer path's Montgomery scale 2^bits / N is 1 / N
+  // here, carried by the same table entries.
+  __device__ __forceinline__ double mont(double x, double y) const { return shoup(x, y, 0.0); }
 };
 
 // ----------------------------------------------------------------------------

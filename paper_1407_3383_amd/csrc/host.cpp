@@ -10,6 +10,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ntt_mi355x.h"
@@ -256,7 +257,8 @@ template <typename T>
 TwPair<T> pair_of(uint64_t w, uint64_t p) {
   TwPair<T> t;
   t.w = (T)w;
-  t.ws = (T)(((u128)w << (8 * sizeof(T))) / p);
+  if constexpr (std::is_same<T, double>::value) t.ws = (double)w / (double)p;  // not read by the FP64 product
+  else t.ws = (T)(((u128)w << (8 * sizeof(T))) / p);
   return t;
 }
 
@@ -299,6 +301,7 @@ struct ntt_plan {
   uint32_t log2n, wbits, flags, passes, L1, L2, B, LT;
   int device;
   bool lazy;
+  bool numeric;  // residues held in doubles (FP64 arithmetic), p < 2^49
   void* dmem;
   size_t dbytes;
   const void *tw, *twi, *tlo, *thi, *tilo, *tihi, *tihin, *polyc, *passc;
@@ -331,14 +334,18 @@ int build_plan_tables(ntt_plan* pl) {
   const size_t o_twi = blob.add(twi.data(), twi.size() * sizeof(TwPair<T>));
 
   const uint64_t N = 1ull << L;
-  const uint64_t sigma = mulmod((uint64_t)((((u128)1) << W) % p), pl->ninv, p);
+  // the scale the entry-wise product removes: 2^W / N for Montgomery's product over
+  // W-bit words, 1 / N for the FP64 product (no Montgomery factor)
+  constexpr bool kNumeric = std::is_same<T, double>::value;
+  const uint64_t sigma = kNumeric ? pl->ninv : mulmod((uint64_t)((((u128)1) << W) % p), pl->ninv, p);
+  const T pinv_word = kNumeric ? (T)(1.0 / (double)p) : (T)inv_pow2_word(p, W);
 
   // Fused-product constants.
   PolyConst<T> pc;
   memset(&pc, 0, sizeof(pc));
   pc.p = (T)p;
   pc.p2 = (T)(2 * p);
-  pc.pinv = (T)inv_pow2_word(p, W);
+  pc.pinv = pinv_word;
   pc.lazy = (T)(pl->lazy ? 1 : 0);
   {
     const int lmax = (W == 32) ? 14 : 13;
@@ -420,7 +427,7 @@ int build_plan_tables(ntt_plan* pl) {
   memset(&sc, 0, sizeof(sc));
   sc.p = (T)p;
   sc.p2 = (T)(2 * p);
-  sc.pinv = (T)inv_pow2_word(p, W);
+  sc.pinv = pinv_word;
   sc.lazy = (T)(pl->lazy ? 1 : 0);
   sc.ninv = pair_of<T>(pl->ninv, p);
   sc.sigma = pair_of<T>(sigma, p);
@@ -473,12 +480,18 @@ const uint64_t kMaxModulus = 1ull << 62;
 
 int check_modulus(uint64_t p, int* l_out) {
   if (p < 3 || p >= kMaxModulus) return fail(NTT_EUNSUPPORTED, "modulus %llu outside [3, 2^62)", (unsigned long long)p);
-  if (!is_prime_u64(p)) return fail(NTT_ENOTPRIME, "modulus %llu is not prime", (unsigned long long)p);
+  // the last modulus found prime (a batch names the same few primes many times)
+  static thread_local uint64_t last_prime = 0;
+  if (p != last_prime) {
+    if (!is_prime_u64(p)) return fail(NTT_ENOTPRIME, "modulus %llu is not prime", (unsigned long long)p);
+    last_prime = p;
+  }
   *l_out = two_adic_order(p);
   return NTT_OK;
 }
 
-int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags, bool product = false) {
+int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t flags, bool product = false,
+                bool numeric = false) {
   if (g_capturing)
     return fail(NTT_EINVAL, "plan for p = %llu, N = 2^%u does not exist yet and cannot be created during a graph "
                 "capture: run the call once before capturing it", (unsigned long long)p, log2n);
@@ -489,6 +502,8 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
   if ((int)log2n > l)
     return fail(NTT_ENOROOT, "2^%u does not divide p - 1 (2-adic order %d)", log2n, l);
   if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE)) return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
+  if (numeric && p >= (1ull << 49))
+    return fail(NTT_EUNSUPPORTED, "FP64 residues need p < 2^49 (p = %llu)", (unsigned long long)p);
   if (g == 0) {
     g = smallest_generator(p);
   } else if (!generates(g, p, distinct_prime_factors(p - 1))) {
@@ -500,8 +515,9 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
   pl->g = g;
   pl->log2n = log2n;
   pl->flags = flags;
-  pl->wbits = p < (1ull << 31) ? 32 : 64;
-  pl->lazy = pl->wbits == 64 ? true : (p < (1ull << 30));
+  pl->numeric = numeric;
+  pl->wbits = (p < (1ull << 31) && !numeric) ? 32 : 64;
+  pl->lazy = numeric ? (p < (1ull << 48)) : (pl->wbits == 64 ? true : (p < (1ull << 30)));
   pl->w = powmod(g, (p - 1) >> log2n, p);
   pl->winv = invmod(pl->w, p);
   pl->ninv = invmod((1ull << log2n) % p, p);
@@ -520,7 +536,8 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
     delete pl;
     return fail(NTT_EDEVICE, "hipGetDevice failed");
   }
-  rc = pl->wbits == 32 ? build_plan_tables<uint32_t>(pl) : build_plan_tables<uint64_t>(pl);
+  rc = numeric ? build_plan_tables<double>(pl)
+               : (pl->wbits == 32 ? build_plan_tables<uint32_t>(pl) : build_plan_tables<uint64_t>(pl));
   if (rc) {
     delete pl;
     return rc;
@@ -562,19 +579,19 @@ DeviceCtx* device_ctx(int dev) {
 }
 
 // Cached plan for (current device, p, log2n) with the smallest generator.
-int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out) {
+int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_EDEVICE, "hipGetDevice failed");
   DeviceCtx* c = device_ctx(dev);
   std::lock_guard<std::mutex> lk(c->mu);
-  auto key = std::make_pair(p, log2n);
+  auto key = std::make_pair(numeric ? (p | (1ull << 63)) : p, log2n);  // FP64 plans: p < 2^49, own key
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = it->second;
     return NTT_OK;
   }
   ntt_plan* pl = nullptr;
-  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, true);
+  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, true, numeric);
   if (rc) return rc;
   c->plans[key] = pl;
   *out = pl;
@@ -1175,6 +1192,7 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
 }  // extern "C"
 
 // ---------------------------------------------------------------------------- reusable batches
+constexpr int kF64Group = -64;  // group word size of residues held in doubles
 struct ntt_batch {
   int device;
   void* ditems;  // device FusedItem array (owned)
@@ -1282,7 +1300,8 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
       fb.items = (const FusedItem*)bt->ditems + g.first;
       fb.park = workspace;
       fb.count = (int)g.count;
-      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), stream));
+      if (g.wb == kF64Group) HIP_TRY(launch_fused_f64(g.cls, fb, fused_grid(64, g.cls, g.count, bt->cus), stream));
+      else HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), stream));
     }
     for (const auto& b : bt->big) {
       int rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, workspace, stream);
@@ -1882,3 +1901,163 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
 
 }  // extern "C"
 
+// ============================================================================ FP64 residues
+namespace {
+
+// Shape checks of one FP64 product: p < 2^49 prime, transform within one workgroup.
+int f64_shape(const ntt_polymul_desc& d, size_t i, ProductShape* s) {
+  if (d.p >= (1ull << 49))
+    return fail(NTT_EUNSUPPORTED, "descriptor %zu: FP64 residues need p < 2^49", i);
+  int rc = shape_of(d.p, d.la, d.lb, s);
+  if (rc) {
+    std::string m = g_last_error;
+    return fail(rc, "descriptor %zu: %s", i, m.c_str());
+  }
+  s->wb = 64;
+  if (s->L > fused_max_log2n(64))
+    return fail(NTT_EUNSUPPORTED, "descriptor %zu: transform length 2^%d exceeds the FP64 limit 2^%d", i, s->L,
+                fused_max_log2n(64));
+  s->fused = true;
+  return NTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int polymul_f64_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t count) {
+  try {
+    if (!out) return fail(NTT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (g_capturing) return fail(NTT_EINVAL, "polymul_f64_batch_create allocates and cannot run during a graph capture");
+    if (count && !d) return fail(NTT_EINVAL, "descriptor array is NULL");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::vector<ProductShape> shapes(count);
+    for (size_t i = 0; i < count; ++i) {
+      if (d[i].la == 0 || d[i].lb == 0) {
+        shapes[i].L = -1;
+        continue;
+      }
+      if (!d[i].a || !d[i].b || !d[i].c) return fail(NTT_EINVAL, "descriptor %zu: NULL operand pointer", i);
+      int rc = f64_shape(d[i], i, &shapes[i]);
+      if (rc) return rc;
+      if (!aligned_to(d[i].a, 8) || !aligned_to(d[i].b, 8) || !aligned_to(d[i].c, 8))
+        return fail(NTT_EINVAL, "descriptor %zu: operands must be 8-byte aligned", i);
+    }
+    ntt_batch* bt = new ntt_batch();
+    bt->device = dev;
+    bt->ditems = nullptr;
+    std::vector<FusedItem> items;
+    for (int cls = 0; cls < 4; ++cls) {
+      const size_t first = items.size();
+      for (size_t i = 0; i < count; ++i) {
+        const ProductShape& s = shapes[i];
+        if (s.L < 0 || fused_class(64, s.L) != cls) continue;
+        ntt_plan* pl = nullptr;
+        int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+        if (rc) {
+          delete bt;
+          return rc;
+        }
+        items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+      }
+      if (items.size() > first) bt->groups.push_back({kF64Group, cls, first, items.size() - first});
+    }
+    bt->cus = current_cus();
+    bt->big_ws = batch_scratch(shapes, bt->cus, nullptr);
+    if (!items.empty()) {
+      if (hipMalloc(&bt->ditems, items.size() * sizeof(FusedItem)) != hipSuccess) {
+        delete bt;
+        return fail(NTT_ENOMEM, "hipMalloc of batch descriptors failed");
+      }
+      if (hipMemcpy(bt->ditems, items.data(), items.size() * sizeof(FusedItem), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(bt->ditems);
+        delete bt;
+        return fail(NTT_EDEVICE, "upload of batch descriptors failed");
+      }
+    }
+    *out = bt;
+    return ok();
+  } catch (...) {
+    return fail(NTT_ENOMEM, "exception in polymul_f64_batch_create");
+  }
+}
+
+size_t polymul_f64_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count) {
+  if (!d && count) return 0;
+  std::vector<ProductShape> shapes(count);
+  for (size_t i = 0; i < count; ++i) {
+    shapes[i].L = -1;
+    if (d[i].la == 0 || d[i].lb == 0) continue;
+    if (f64_shape(d[i], i, &shapes[i])) shapes[i].L = -1;
+  }
+  size_t nfused = 0;
+  const size_t scratch = batch_scratch(shapes, current_cus(), &nfused);
+  return align256(nfused * sizeof(FusedItem)) + scratch;
+}
+
+int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (capturing(stream))
+      return fail(NTT_EINVAL, "polymul_f64_batch copies host descriptors and cannot be captured in a graph");
+    if (count == 0) return ok();
+    if (!d) return fail(NTT_EINVAL, "descriptor array is NULL");
+    std::vector<ProductShape> shapes(count);
+    for (size_t i = 0; i < count; ++i) {
+      if (d[i].la == 0 || d[i].lb == 0) {
+        shapes[i].L = -1;
+        continue;
+      }
+      if (!d[i].a || !d[i].b || !d[i].c) return fail(NTT_EINVAL, "descriptor %zu: NULL operand pointer", i);
+      int rc = f64_shape(d[i], i, &shapes[i]);
+      if (rc) return rc;
+      if (!aligned_to(d[i].a, 8) || !aligned_to(d[i].b, 8) || !aligned_to(d[i].c, 8))
+        return fail(NTT_EINVAL, "descriptor %zu: operands must be 8-byte aligned", i);
+    }
+    const int cus = current_cus();
+    size_t nfused = 0;
+    const size_t scratch = batch_scratch(shapes, cus, &nfused);
+    const size_t need = align256(nfused * sizeof(FusedItem)) + scratch;
+    if (ws_bytes < need || (need && !workspace))
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    DeviceCtx* ctx = device_ctx(dev);
+    std::vector<FusedItem> items;
+    items.reserve(nfused);
+    struct Group { int cls; size_t first, count; };
+    std::vector<Group> groups;
+    for (int cls = 0; cls < 4; ++cls) {
+      const size_t first = items.size();
+      for (size_t i = 0; i < count; ++i) {
+        const ProductShape& s = shapes[i];
+        if (s.L < 0 || fused_class(64, s.L) != cls) continue;
+        ntt_plan* pl = nullptr;
+        int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+        if (rc) return rc;
+        items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+      }
+      if (items.size() > first) groups.push_back({cls, first, items.size() - first});
+    }
+    if (items.empty()) return ok();
+    FusedItem* ditems = (FusedItem*)workspace;
+    int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
+    if (rc) return rc;
+    void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
+    for (const Group& g : groups) {
+      FusedBatch fb;
+      memset(&fb, 0, sizeof(fb));
+      fb.items = ditems + g.first;
+      fb.park = bigws;
+      fb.count = (int)g.count;
+      HIP_TRY(launch_fused_f64(g.cls, fb, fused_grid(64, g.cls, g.count, cus), stream));
+    }
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymul_f64_batch");
+  }
+}
+
+}  // extern "C"

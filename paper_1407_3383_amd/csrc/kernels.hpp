@@ -21,6 +21,8 @@ int fused_max_log2n(int word_bits);
 size_t fused_park_words(int word_bits, int cls);
 int fused_grid(int word_bits, int cls, size_t count, int cus);
 hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int grid, hipStream_t stream);
+// Residues held in doubles, p < 2^49 (classes and grids of the 64-bit word size).
+hipError_t launch_fused_f64(int cls, const FusedBatch& batch, int grid, hipStream_t stream);
 
 // Transform of `batch` vectors that fit one workgroup's LDS (log2n <= lds_max_log2n).
 struct LdsNttArgs {

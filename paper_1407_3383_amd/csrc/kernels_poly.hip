@@ -532,4 +532,14 @@ hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int gri
   return hipErrorInvalidValue;
 }
 
+// The same kernels over residues held in doubles (the 64-bit word classes).
+hipError_t launch_fused_f64(int cls, const FusedBatch& batch, int grid, hipStream_t stream) {
+  switch (cls) {
+    case 0: return launch_fused_cls<double, 64, 10, 0, 0, 0>(batch, grid, stream);
+    case 1: return launch_fused_cls<double, 256, 12, 11, 0, 0>(batch, grid, stream);
+    case 3: return launch_fused_cls<double, 512, 13, 13, 2, 0>(batch, grid, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace nttgpu

@@ -44,7 +44,8 @@ EXPORTS = (
     "polymul_batch_workspace_bytes", "polymul_modp_batch", "polymul_batch_create",
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
-    "polymatmul_workspace_bytes", "polymatmul_modp",
+    "polymatmul_workspace_bytes", "polymatmul_modp", "polymul_f64_batch_workspace_bytes", "polymul_f64_batch",
+    "polymul_f64_batch_create",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
@@ -111,6 +112,9 @@ def load(path: str = LIB_PATH):
         "intmul_crt32": (ci, [vp, sz, vp, sz, vp, vp, sz, vp]),
         "polymatmul_workspace_bytes": (sz, [u64, sz, sz]),
         "polymatmul_modp": (ci, [u64, sz, vp, vp, sz, vp, vp, sz, vp]),
+        "polymul_f64_batch_workspace_bytes": (sz, [ctypes.POINTER(PolymulDesc), sz]),
+        "polymul_f64_batch": (ci, [ctypes.POINTER(PolymulDesc), sz, vp, sz, vp]),
+        "polymul_f64_batch_create": (ci, [ctypes.POINTER(vp), ctypes.POINTER(PolymulDesc), sz]),
         "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
         "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
         "ntt_tune_clear": (ci, []),
@@ -274,6 +278,36 @@ def polymul_batch(pairs: Sequence, primes: Sequence[int], outs=None, stream=None
     return outs
 
 
+def polymul_f64_rows(A, B, p: int, out=None, stream=None, workspace=None, descs=None):
+    """Row-wise products of two [items, L] float64 matrices of residues mod p < 2^49,
+    computed in FP64 arithmetic (polymul_f64_batch); out is [items, la + lb - 1] float64."""
+    torch = _torch()
+    items, la = A.shape
+    lb = B.shape[1]
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise ValueError("operands must be float64 residues")
+    if out is None:
+        out = torch.empty((items, la + lb - 1), dtype=torch.float64, device=A.device)
+    L = load()
+    if descs is None:
+        descs = f64_row_descs(A, B, out, p)
+    need = L.polymul_f64_batch_workspace_bytes(descs, items)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, A.device)
+    _check(L.polymul_f64_batch(descs, items, _ptr(ws), ws.numel() if ws is not None else 0, _stream(stream)),
+           "polymul_f64_batch")
+    return out
+
+
+def f64_row_descs(A, B, out, p: int):
+    items, la = A.shape
+    lb = B.shape[1]
+    descs = (PolymulDesc * items)()
+    a0, b0, c0 = A.data_ptr(), B.data_ptr(), out.data_ptr()
+    for i in range(items):
+        descs[i] = PolymulDesc(p, a0 + 8 * la * i, la, b0 + 8 * lb * i, lb, c0 + 8 * out.shape[1] * i)
+    return descs
+
+
 def polymul_rows(A, B, p: int, out=None, stream=None, workspace=None):
     """Row-wise products of two [items, L] matrices (one batched launch)."""
     torch = _torch()
@@ -299,7 +333,8 @@ class Batch:
     """Reusable batch handle (polymul_batch_create): descriptors live on the device;
     each call only launches kernels, so it can be repeated or graph-captured."""
 
-    def __init__(self, pairs_or_descs, primes=None, outs=None):
+    def __init__(self, pairs_or_descs, primes=None, outs=None, f64=False):
+        """f64: operands and outputs are float64 residues (polymul_f64_batch_create)."""
         L = load()
         if primes is not None:
             descs = (PolymulDesc * max(len(pairs_or_descs), 1))()
@@ -310,14 +345,17 @@ class Batch:
         else:
             descs, count = pairs_or_descs
         h = ctypes.c_void_p()
-        _check(L.polymul_batch_create(ctypes.byref(h), descs, count), "polymul_batch_create")
+        if f64:
+            _check(L.polymul_f64_batch_create(ctypes.byref(h), descs, count), "polymul_f64_batch_create")
+        else:
+            _check(L.polymul_batch_create(ctypes.byref(h), descs, count), "polymul_batch_create")
         self.handle = h
         self.count = count
         self.ws_bytes = int(L.polymul_batch_launch_workspace_bytes(h))
         self.ws = None
 
     @classmethod
-    def rows(cls, A, B, out, p: int):
+    def rows(cls, A, B, out, p: int, f64: bool = False):
         """Row-wise products of [items, L] matrices into out[items, La + Lb - 1]."""
         items, la = A.shape
         lb = B.shape[1]
@@ -327,7 +365,7 @@ class Batch:
             descs[i] = PolymulDesc(p, A.data_ptr() + i * A.stride(0) * esz, la,
                                    B.data_ptr() + i * B.stride(0) * esz, lb,
                                    out.data_ptr() + i * out.stride(0) * esz)
-        self = cls((descs, items))
+        self = cls((descs, items), f64=f64)
         self._keep = (A, B, out)
         if self.ws_bytes:
             self.ws = _workspace(self.ws_bytes, A.device)

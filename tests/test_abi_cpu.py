@@ -166,3 +166,21 @@ def test_polymatmul_argument_errors_and_sizes(lib):
     assert lib.polymatmul_modp(7340033, 2, one, one, (1 << 19) + 1, one, None, 0, None) == ntt.NTT_ENOROOT
     assert lib.polymatmul_workspace_bytes(7340033, 2, (1 << 19) + 1) == 0
     assert lib.polymatmul_modp(p, 3, one, one, 10, one, None, 0, None) == ntt.NTT_ENOMEM
+
+
+def test_f64_batch_argument_errors(lib):
+    one = 16
+    descs = (ntt.PolymulDesc * 1)()
+    descs[0] = ntt.PolymulDesc(63 * 2 ** 44 + 1, one, 8, one, 8, one)       # p >= 2^49
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.polymul_f64_batch_workspace_bytes(descs, 1) == 0
+    p49 = ntt.find_prime(49, 20)
+    descs[0] = ntt.PolymulDesc(p49, one, 1 << 15, one, 1 << 15, one)         # transform 2^16
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EUNSUPPORTED
+    descs[0] = ntt.PolymulDesc(p49, one, 8, one, 8, one)
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_ENOMEM
+    assert lib.polymul_f64_batch_workspace_bytes(descs, 1) >= 64
+    descs[0] = ntt.PolymulDesc(p49, one + 4, 8, one, 8, one)
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EINVAL
+    descs[0] = ntt.PolymulDesc(p49 + 2, one, 8, one, 8, one)
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) in (ntt.NTT_ENOTPRIME, ntt.NTT_ENOROOT)
