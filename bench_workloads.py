@@ -180,6 +180,8 @@ def run(name, args):
         return run_polymatrix(args)
     if name == "f64":
         return run_f64(args)
+    if name == "intmatrix":
+        return run_intmatrix(args)
     if name == "serve":
         return run_serve(args)
     raise ValueError(name)
@@ -372,3 +374,44 @@ def run_f64(args):
                  {"workload": "1024 products of length-2^14 operands, transform length 2^15, p < 2^49 and p < 2^48"},
                  {"dtype": "f64", "by_case": res,
                   "note": "u64: the same batch with 64-bit integer residues (Function 8 over 64-bit words)"})
+
+
+# Section 5.3's table of integer matrix products in bit-size 32 x 2^15 (seconds on one
+# core of the paper's machine), for context beside the times here
+PAPER_INTMATRIX_S = {1: 0.0060, 2: 0.022, 4: 0.095, 8: 0.44, 16: 2.3, 32: 13}
+
+
+def run_intmatrix(args):
+    """n x n integer matrix products, entries of 32 x 2^15 bits (2^15 chunks of 32
+    bits): three polynomial matrix products of transform length 2^16 and a batched CRT
+    tail, n = 1 .. 32."""
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt
+    stream = torch.cuda.Stream()
+    na = 1 << 15
+    L = ntt.load()
+    rows = {}
+    sizes = (1, 2, 4, 8, 16, 32) if not args.matrix_n else (args.matrix_n,)
+    for n in sizes:
+        A = inputs.limbs32(n * n * na, inputs.CFG_TEST, 88000 + n, 0)
+        B = inputs.limbs32(n * n * na, inputs.CFG_TEST, 88000 + n, 1)
+        dA = ntt.to_device(A).reshape(n, n, na)
+        dB = ntt.to_device(B).reshape(n, n, na)
+        dC = torch.empty((n, n, 2 * na + 1), dtype=torch.int32, device="cuda")
+        ws = torch.empty(L.intmatmul32_workspace_bytes(n, na), dtype=torch.uint8, device="cuda")
+
+        def step():
+            ntt._check(L.intmatmul_crt32(n, ntt._ptr(dA), ntt._ptr(dB), na, ntt._ptr(dC), ntt._ptr(ws), ws.numel(),
+                                         ntt._stream(stream)), "intmatmul_crt32")
+        _, kms = _time(step, stream, max(args.steps, 10), 2)
+        rows[n] = {"ms": round(kms, 4), "paper_cpu_s": PAPER_INTMATRIX_S.get(n)}
+        _log("intmatrix n=%d: %.4f ms" % (n, kms))
+        del dA, dB, dC, ws
+    top = rows[max(rows)]
+    return _line("integer matrix product %d x %d, entries of 32 x 2^15 bits (ms per product)" % (max(rows), max(rows)),
+                 top["ms"], "ms", top["ms"], max(args.steps, 10), 2,
+                 {"workload": "n x n matrices of 2^20-bit integers, 32-bit chunks, primes 998244353, 469762049, "
+                              "167772161, transform length 2^16"},
+                 {"higher_is_better": False, "by_n": rows,
+                  "note": "paper_cpu_s: the section's table, one core of the paper's machine (context, not a target)"})

@@ -306,6 +306,23 @@ size_t polymatmul_workspace_bytes(uint64_t p, size_t n, size_t d);
 int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
                     size_t ws_bytes, void* hip_stream);
 
+/* Integer matrix product (section 5.3): C = A B for n x n matrices of nonnegative
+ * integers, through Kronecker segmentation into chunks of 32 bits (section 5.3's
+ * chunk size for these primes), the polynomial matrix product modulo each of
+ * 998244353, 469762049 and 167772161 (polymatmul_modp), and per entry Garner's
+ * reconstruction and the carries.
+ * A, B: device, n*n entries of na little-endian 32-bit limbs each, entry (i, j) at
+ *   offset (i*n + j)*na.  C: device, n*n entries of 2*na + 1 limbs, entry (i, j) at
+ *   (i*n + j)*(2*na + 1), unnormalised (leading zero limbs).
+ * 1 <= n <= 64; n * na * (2^32 - 1)^2 < p1 p2 p3 (about 2^86; n = 32 allows na up to
+ *   2^16) and 2*na - 1 <= 2^23.  workspace: intmatmul32_workspace_bytes(n, na) bytes.
+ * n == 0 or na == 0: nothing to do, NTT_OK.
+ * Errors: NTT_EINVAL (pointers, sizes beyond the bounds), NTT_EUNSUPPORTED (n > 64),
+ *   NTT_ENOMEM (workspace), NTT_EDEVICE. */
+size_t intmatmul32_workspace_bytes(size_t n, size_t na);
+int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, uint32_t* C, void* workspace,
+                    size_t ws_bytes, void* hip_stream);
+
 /* Products mod p with residues held in doubles (section 3: modular arithmetic over
  * numeric types; products by Function 16, the FMA product, sums by Function 17's
  * compare-and-subtract), in the same fused one-workgroup kernels as polymul_modp_batch.

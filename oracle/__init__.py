@@ -258,6 +258,29 @@ def intmul_pyint(a16, b16) -> np.ndarray:
     return np.frombuffer((A * B).to_bytes(4 * nc32, "little"), dtype="<u4").astype(np.uint32)
 
 
+def _int_of_limbs32(x) -> int:
+    return int.from_bytes(np.ascontiguousarray(np.asarray(x, dtype="<u4")).tobytes(), "little")
+
+
+def intmatmul_entry_pyint(A32, B32, i: int, j: int) -> int:
+    """Entry (i, j) of the integer matrix product (section 5.3) as a Python integer:
+    sum over l of A[i, l] B[l, j], each entry a little-endian 32-bit limb vector."""
+    n = A32.shape[0]
+    return sum(_int_of_limbs32(A32[i, l]) * _int_of_limbs32(B32[l, j]) for l in range(n))
+
+
+def intmatmul_pyint(A32, B32) -> np.ndarray:
+    """Integer matrix product (section 5.3): A, B of shape (n, n, na) 32-bit limbs ->
+    C of shape (n, n, 2 na + 1) limbs, exactly, with Python's integers."""
+    n, na = A32.shape[0], A32.shape[2]
+    out = np.zeros((n, n, 2 * na + 1), dtype=np.uint32)
+    for i in range(n):
+        for j in range(n):
+            v = intmatmul_entry_pyint(A32, B32, i, j)
+            out[i, j] = np.frombuffer(v.to_bytes(4 * (2 * na + 1), "little"), dtype="<u4")
+    return out
+
+
 def garner_digits(r1, r2, r3, primes=INTMUL_PRIMES):
     """Garner's mixed-radix digits (x1, x2, x3) of each residue triple."""
     v1, v2, v3 = _u64(r1), _u64(r2), _u64(r3)

@@ -1593,6 +1593,24 @@ namespace {
 // p1 p2 p3 of the three primes (a bit over 2^86).
 u128 int_prime_product() { return (u128)kIntPrimes[0] * kIntPrimes[1] * kIntPrimes[2]; }
 
+// Garner constants of the three primes (p1^-1 mod p2, (p1 p2)^-1 mod p3, p1 mod p3,
+// with their Function 8 companions) for the 32-bit-chunk tail.
+void crt_constants(CrtArgs* x) {
+  const uint64_t p1 = kIntPrimes[0], p2 = kIntPrimes[1], p3 = kIntPrimes[2];
+  x->p1 = (uint32_t)p1;
+  x->p2 = (uint32_t)p2;
+  x->p3 = (uint32_t)p3;
+  const uint64_t c12 = invmod(p1 % p2, p2);
+  const uint64_t c123 = invmod(mulmod(p1 % p3, p2 % p3, p3), p3);
+  x->c12 = (uint32_t)c12;
+  x->c12s = (uint32_t)((c12 << 32) / p2);
+  x->c123 = (uint32_t)c123;
+  x->c123s = (uint32_t)((c123 << 32) / p3);
+  x->p1m3 = (uint32_t)(p1 % p3);
+  x->p1m3s = (uint32_t)(((p1 % p3) << 32) / p3);
+  x->p1p2 = p1 * p2;
+}
+
 struct Int32Layout {
   size_t lc, npos, N, nblk;
   int L;
@@ -1709,6 +1727,7 @@ int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uin
     }
     CrtArgs x;
     memset(&x, 0, sizeof(x));
+    crt_constants(&x);
     x.r1 = r[0];
     x.r2 = r[1];
     x.r3 = r[2];
@@ -1717,19 +1736,6 @@ int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uin
     x.t = (uint32_t*)(w + z.o_t);
     x.blk = (uint32_t*)(w + z.o_blk);
     x.c = c;
-    const uint64_t p1 = kIntPrimes[0], p2 = kIntPrimes[1], p3 = kIntPrimes[2];
-    x.p1 = (uint32_t)p1;
-    x.p2 = (uint32_t)p2;
-    x.p3 = (uint32_t)p3;
-    const uint64_t c12 = invmod(p1 % p2, p2);
-    const uint64_t c123 = invmod(mulmod(p1 % p3, p2 % p3, p3), p3);
-    x.c12 = (uint32_t)c12;
-    x.c12s = (uint32_t)((c12 << 32) / p2);
-    x.c123 = (uint32_t)c123;
-    x.c123s = (uint32_t)((c123 << 32) / p3);
-    x.p1m3 = (uint32_t)(p1 % p3);
-    x.p1m3s = (uint32_t)(((p1 % p3) << 32) / p3);
-    x.p1p2 = p1 * p2;
     HIP_TRY(launch_crt32_carry(x, stream));
     return ok();
   } catch (...) {
@@ -1896,6 +1902,109 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
     return ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in polymatmul_modp");
+  }
+}
+
+}  // extern "C"
+
+// ============================================================================ integer matrices
+namespace {
+
+struct IntMatLayout {
+  size_t lc, npos, nblk, o_ar, o_br, o_r[3], o_pm, o_t, o_blk, total;
+};
+
+// n x n matrices of na-chunk integers: coefficients of C's entries are sums of n
+// products of two chunk polynomials, below n na (2^32 - 1)^2 < p1 p2 p3.
+bool intmat_fits(size_t n, size_t na) {
+  if (n == 0 || n > kMatMaxN || na == 0 || 2 * na - 1 > ((size_t)1 << 23)) return false;
+  const u128 P = (u128)kIntPrimes[0] * kIntPrimes[1] * kIntPrimes[2];
+  const u128 m = (u128)0xFFFFFFFFull * 0xFFFFFFFFull;
+  return (u128)n * na <= P / m && (u128)n * na * m < P;
+}
+
+IntMatLayout intmat_layout(size_t n, size_t na) {
+  IntMatLayout z;
+  memset(&z, 0, sizeof(z));
+  const size_t n2 = n * n;
+  z.lc = 2 * na - 1;
+  z.npos = 2 * na + 1;  // a sum of n products can carry one limb past 2 na
+  z.nblk = (z.npos + crt_block_positions() - 1) / crt_block_positions();
+  size_t off = 0;
+  z.o_ar = off;
+  off += align256(n2 * na * 4);
+  z.o_br = off;
+  off += align256(n2 * na * 4);
+  for (int i = 0; i < 3; ++i) {
+    z.o_r[i] = off;
+    off += align256(n2 * z.lc * 4);
+  }
+  z.o_pm = off;
+  off += polymatmul_workspace_bytes(kIntPrimes[0], n, na);
+  z.o_t = off;
+  off += align256(n2 * z.nblk * crt_block_positions() * 8);
+  z.o_blk = off;
+  off += align256(n2 * z.nblk * 4);
+  z.total = off;
+  return z;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t intmatmul32_workspace_bytes(size_t n, size_t na) {
+  if (!intmat_fits(n, na)) return 0;
+  return intmat_layout(n, na).total;
+}
+
+int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, uint32_t* C, void* workspace,
+                    size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (n == 0 || na == 0) return ok();
+    if (!A || !B || !C) return fail(NTT_EINVAL, "NULL matrix pointer");
+    if (!aligned_to(A, 4) || !aligned_to(B, 4) || !aligned_to(C, 4)) return fail(NTT_EINVAL, "misaligned pointer");
+    if (n > kMatMaxN) return fail(NTT_EUNSUPPORTED, "n = %zu exceeds %u", n, kMatMaxN);
+    if (!intmat_fits(n, na))
+      return fail(NTT_EINVAL, "n = %zu, %zu chunks: coefficients could reach p1 p2 p3 or the transform exceed 2^23",
+                  n, na);
+    const IntMatLayout z = intmat_layout(n, na);
+    if (ws_bytes < z.total || !workspace)
+      return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", z.total, ws_bytes);
+    unsigned char* w = (unsigned char*)workspace;
+    uint32_t* ar = (uint32_t*)(w + z.o_ar);
+    uint32_t* br = (uint32_t*)(w + z.o_br);
+    const size_t n2 = n * n;
+    const size_t pm_bytes = polymatmul_workspace_bytes(kIntPrimes[0], n, na);
+    for (int i = 0; i < 3; ++i) {
+      // chunks of 32 bits exceed the primes: residues first, then the polynomial
+      // matrix product modulo this prime
+      HIP_TRY(launch_reduce_mod(A, ar, n2 * na, kIntPrimes[i], stream));
+      HIP_TRY(launch_reduce_mod(B, br, n2 * na, kIntPrimes[i], stream));
+      int rc = polymatmul_modp(kIntPrimes[i], n, ar, br, na, w + z.o_r[i], w + z.o_pm, pm_bytes, stream);
+      if (rc) return rc;
+    }
+    CrtArgs x;
+    memset(&x, 0, sizeof(x));
+    crt_constants(&x);
+    x.r1 = (const uint32_t*)(w + z.o_r[0]);
+    x.r2 = (const uint32_t*)(w + z.o_r[1]);
+    x.r3 = (const uint32_t*)(w + z.o_r[2]);
+    x.lc = z.lc;
+    x.npos = z.npos;
+    x.t = (uint32_t*)(w + z.o_t);
+    x.blk = (uint32_t*)(w + z.o_blk);
+    x.c = C;
+    x.rstride = z.lc;
+    x.tstride = z.nblk * crt_block_positions();
+    x.bstride = (uint32_t)z.nblk;
+    x.cstride = z.npos;
+    x.batch = (uint32_t)n2;
+    HIP_TRY(launch_crt32_carry(x, stream));
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in intmatmul_crt32");
   }
 }
 

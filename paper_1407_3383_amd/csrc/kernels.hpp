@@ -129,6 +129,10 @@ struct CrtArgs {
   uint32_t c123, c123s;  // (p1 p2)^-1 mod p3 and companion
   uint32_t p1m3, p1m3s;  // p1 mod p3 and companion
   uint64_t p1p2;
+  // batches of independent integers (32-bit chunk tail only): entry e = blockIdx.y
+  // reads r_k + e rstride, uses t + e tstride and blk + e bstride, writes c + e cstride
+  uint64_t rstride, tstride, cstride;
+  uint32_t bstride, batch;  // batch 0 or 1: one integer
 };
 int crt_block_positions();
 hipError_t launch_crt_carry(const CrtArgs& a, hipStream_t stream);

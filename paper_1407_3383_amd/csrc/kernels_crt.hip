@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kCrtNT) void crt_phase1_kernel(CrtArgs A) {
 // Phase 2 (one workgroup): block statuses -> carry into each block.
 __global__ __launch_bounds__(1024) void crt_phase2_kernel(CrtArgs A, uint32_t nblk) {
   __shared__ uint32_t wsum[16];
-  gptr<uint32_t> blk = gmut<uint32_t>(A.blk);
+  gptr<uint32_t> blk = gmut<uint32_t>(A.blk) + (uint64_t)blockIdx.y * A.bstride;
   const uint32_t per = (nblk + 1023) / 1024;  // at most 8: the host caps nblk at 8192
   const uint32_t b0 = threadIdx.x * per;
   uint32_t st[8];
@@ -222,9 +222,10 @@ __global__ __launch_bounds__(kCrtNT) void crt32_phase1_kernel(CrtArgs A) {
   __shared__ uint32_t vhi[kCrtBlock + kCrt32Halo];
   __shared__ uint32_t wmax[kCrtNT / 64];
   const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
-  gcptr<uint32_t> r1 = gconst<uint32_t>(A.r1);
-  gcptr<uint32_t> r2 = gconst<uint32_t>(A.r2);
-  gcptr<uint32_t> r3 = gconst<uint32_t>(A.r3);
+  const uint64_t e = blockIdx.y;
+  gcptr<uint32_t> r1 = gconst<uint32_t>(A.r1) + e * A.rstride;
+  gcptr<uint32_t> r2 = gconst<uint32_t>(A.r2) + e * A.rstride;
+  gcptr<uint32_t> r3 = gconst<uint32_t>(A.r3) + e * A.rstride;
   for (int j = threadIdx.x; j < kCrtBlock + kCrt32Halo; j += kCrtNT) {
     const int64_t k = (int64_t)mb - kCrt32Halo + j;
     uint64_t lo = 0;
@@ -235,7 +236,7 @@ __global__ __launch_bounds__(kCrtNT) void crt32_phase1_kernel(CrtArgs A) {
   }
   __syncthreads();
   uint32_t key = 0;
-  gptr<uint64_t> t = gmut<uint64_t>(A.t);
+  gptr<uint64_t> t = gmut<uint64_t>(A.t) + e * A.tstride;
 #pragma unroll
   for (int q = 0; q < kCrtPPT; ++q) {
     const int lp = threadIdx.x + kCrtNT * q;  // position mb + lp: v_(m-i) at local lp + 3 - i
@@ -252,15 +253,16 @@ __global__ __launch_bounds__(kCrtNT) void crt32_phase1_kernel(CrtArgs A) {
     uint32_t k = 0;
 #pragma unroll
     for (int w = 0; w < kCrtNT / 64; ++w) k = max(k, wmax[w]);
-    gmut<uint32_t>(A.blk)[blockIdx.x] = k == 0 ? 2u : (k & 1u);
+    gmut<uint32_t>(A.blk)[e * A.bstride + blockIdx.x] = k == 0 ? 2u : (k & 1u);
   }
 }
 
 __global__ __launch_bounds__(kCrtNT) void crt32_phase3_kernel(CrtArgs A) {
   __shared__ uint32_t wsum[kCrtNT / 64];
   const uint64_t mb = (uint64_t)blockIdx.x * kCrtBlock;
+  const uint64_t e = blockIdx.y;
   const uint32_t lp0 = threadIdx.x * kCrtPPT;
-  const uint64_t* tv = (const uint64_t*)A.t + mb + lp0;  // the workspace holds whole blocks
+  const uint64_t* tv = (const uint64_t*)A.t + e * A.tstride + mb + lp0;  // the workspace holds whole blocks
   uint64_t t[kCrtPPT];
 #pragma unroll
   for (int q = 0; q < kCrtPPT; ++q) t[q] = tv[q];
@@ -275,8 +277,8 @@ __global__ __launch_bounds__(kCrtNT) void crt32_phase3_kernel(CrtArgs A) {
   for (int i = 0; i < w; ++i) below = max(below, wsum[i]);
   const uint32_t up = (uint32_t)__shfl_up((int)incl, 1, 64);
   const uint32_t excl = max(below, lane > 0 ? up : 0u);
-  uint64_t carry = excl == 0 ? gconst<uint32_t>(A.blk)[blockIdx.x] : (excl & 1u);
-  gptr<uint32_t> c = gmut<uint32_t>(A.c);
+  uint64_t carry = excl == 0 ? gconst<uint32_t>(A.blk)[e * A.bstride + blockIdx.x] : (excl & 1u);
+  gptr<uint32_t> c = gmut<uint32_t>(A.c) + e * A.cstride;
 #pragma unroll
   for (int q = 0; q < kCrtPPT; ++q) {
     const uint64_t x = t[q] + carry;
@@ -290,9 +292,13 @@ hipError_t launch_crt32_carry(const CrtArgs& a, hipStream_t stream) {
   const uint64_t nblk = (a.npos + kCrtBlock - 1) / kCrtBlock;
   if (nblk == 0) return hipSuccess;
   if (nblk > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(crt32_phase1_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);
-  hipLaunchKernelGGL(crt_phase2_kernel, dim3(1), dim3(1024), 0, stream, a, (uint32_t)nblk);
-  hipLaunchKernelGGL(crt32_phase3_kernel, dim3((unsigned)nblk), dim3(kCrtNT), 0, stream, a);
+  const uint32_t batch = a.batch > 1 ? a.batch : 1u;
+  if (batch > 65535) return hipErrorInvalidValue;
+  if (batch > 1 && (a.tstride < nblk * kCrtBlock || a.bstride < nblk || a.cstride < a.npos || a.rstride < a.lc))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(crt32_phase1_kernel, dim3((unsigned)nblk, batch), dim3(kCrtNT), 0, stream, a);
+  hipLaunchKernelGGL(crt_phase2_kernel, dim3(1, batch), dim3(1024), 0, stream, a, (uint32_t)nblk);
+  hipLaunchKernelGGL(crt32_phase3_kernel, dim3((unsigned)nblk, batch), dim3(kCrtNT), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -51,6 +51,12 @@ def limbs16(n: int, config_id: int, item: int = 0, stream: int = 0, top_nonzero:
     return x
 
 
+def limbs32(n: int, config_id: int, item: int = 0, stream: int = 0) -> np.ndarray:
+    """n little-endian 32-bit limbs, uniform in [0, 2^32)."""
+    g = rng(config_id, item * 4 + stream)
+    return g.integers(0, 1 << 32, size=n, dtype=np.uint64).astype(np.uint32)
+
+
 def polymul_8k_inputs():
     """Two length-4096 operands mod 998244353."""
     p = P_998

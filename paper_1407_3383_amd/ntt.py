@@ -45,7 +45,7 @@ EXPORTS = (
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
     "polymatmul_workspace_bytes", "polymatmul_modp", "polymul_f64_batch_workspace_bytes", "polymul_f64_batch",
-    "polymul_f64_batch_create",
+    "polymul_f64_batch_create", "intmatmul32_workspace_bytes", "intmatmul_crt32",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
@@ -115,6 +115,8 @@ def load(path: str = LIB_PATH):
         "polymul_f64_batch_workspace_bytes": (sz, [ctypes.POINTER(PolymulDesc), sz]),
         "polymul_f64_batch": (ci, [ctypes.POINTER(PolymulDesc), sz, vp, sz, vp]),
         "polymul_f64_batch_create": (ci, [ctypes.POINTER(vp), ctypes.POINTER(PolymulDesc), sz]),
+        "intmatmul32_workspace_bytes": (sz, [sz, sz]),
+        "intmatmul_crt32": (ci, [sz, vp, vp, sz, vp, vp, sz, vp]),
         "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
         "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
         "ntt_tune_clear": (ci, []),
@@ -437,6 +439,23 @@ def polymatmul(A, B, p: int, out=None, stream=None, workspace=None):
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, A.device)
     _check(L.polymatmul_modp(p, n, _ptr(A), _ptr(B), d, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                              _stream(stream)), "polymatmul_modp")
+    return out
+
+
+def intmatmul32(A, B, out=None, stream=None, workspace=None):
+    """Integer matrix product (section 5.3): A, B device int32 tensors of shape
+    (n, n, na) holding little-endian 32-bit limbs -> C of shape (n, n, 2 na + 1)."""
+    torch = _torch()
+    L = load()
+    if A.dim() != 3 or A.shape != B.shape or A.shape[0] != A.shape[1]:
+        raise ValueError("A and B must both have shape (n, n, na)")
+    n, na = int(A.shape[0]), int(A.shape[2])
+    if out is None:
+        out = torch.empty((n, n, 2 * na + 1), dtype=torch.int32, device=A.device)
+    need = L.intmatmul32_workspace_bytes(n, na)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, A.device)
+    _check(L.intmatmul_crt32(n, _ptr(A), _ptr(B), na, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
+                             _stream(stream)), "intmatmul_crt32")
     return out
 
 

@@ -184,3 +184,15 @@ def test_f64_batch_argument_errors(lib):
     assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EINVAL
     descs[0] = ntt.PolymulDesc(p49 + 2, one, 8, one, 8, one)
     assert lib.polymul_f64_batch(descs, 1, None, 0, None) in (ntt.NTT_ENOTPRIME, ntt.NTT_ENOROOT)
+
+
+def test_intmatmul_argument_errors_and_sizes(lib):
+    one = ctypes.c_void_p(16)
+    assert lib.intmatmul_crt32(0, one, one, 5, one, None, 0, None) == ntt.NTT_OK
+    assert lib.intmatmul_crt32(65, one, one, 1, one, None, 0, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.intmatmul_crt32(64, one, one, 1 << 17, one, None, 0, None) == ntt.NTT_EINVAL   # n na > 2^22
+    assert lib.intmatmul_crt32(2, one, one, 2, one, None, 0, None) == ntt.NTT_ENOMEM
+    assert lib.intmatmul_crt32(2, ctypes.c_void_p(18), one, 2, one, None, 0, None) == ntt.NTT_EINVAL
+    # the section's table: 32 x 32 entries of 2^15 chunks fit (32 2^15 (2^32 - 1)^2 < p1 p2 p3)
+    assert lib.intmatmul32_workspace_bytes(32, 1 << 15) > 3 * 32 * 32 * ((1 << 16) - 1) * 4
+    assert lib.intmatmul32_workspace_bytes(64, 1 << 17) == 0

@@ -3,7 +3,9 @@ not go through its own formula: evaluation at random points (a ring morphism
 F_p[x] -> F_p, so C(x) = A(x) B(x) as matrices over F_p), the degree-0 case (an
 ordinary matrix product, numpy over Python integers), the 1 x 1 case (the
 polynomial product), the transpose law (A B)^T = B^T A^T (F_p[x] is commutative),
-the identity matrix, and the distributive law."""
+the identity matrix, and the distributive law.  The integer matrix product of
+section 5.3 is pinned by its images modulo random 61-bit q, a closed form and the
+1 x 1 and identity cases."""
 import numpy as np
 import pytest
 
@@ -105,3 +107,46 @@ def test_64_bit_prime():
         for j in range(n):
             want = sum(_eval_py(A[i, l], x, p) * _eval_py(B[l, j], x, p) for l in range(n)) % p
             assert _eval_py(C[i, j], x, p) == want
+
+
+# ---------------------------------------------------------------- integer matrices
+
+def _limbs(n, na, item, stream):
+    return inputs.limbs32(n * n * na, inputs.CFG_TEST, item, stream).reshape(n, n, na)
+
+
+def test_integer_matrix_product_modular_images():
+    """C mod q = (A mod q)(B mod q) mod q for random 61-bit q (a ring morphism Z -> Z/q),
+    the matrix product over Z/q taken by numpy over Python integers."""
+    n, na = 3, 9
+    A, B = _limbs(n, na, 9900, 0), _limbs(n, na, 9900, 1)
+    C = oracle.intmatmul_pyint(A, B)
+    g = np.random.default_rng(5)
+    for _ in range(3):
+        q = int(g.integers(2 ** 60, 2 ** 61)) | 1
+        am = np.array([[oracle.limbs32_mod(A[i, l], q) for l in range(n)] for i in range(n)], dtype=object)
+        bm = np.array([[oracle.limbs32_mod(B[i, l], q) for l in range(n)] for i in range(n)], dtype=object)
+        want = am.dot(bm) % q
+        got = np.array([[oracle.limbs32_mod(C[i, j], q) for j in range(n)] for i in range(n)], dtype=object)
+        assert (got == want).all()
+
+
+def test_integer_matrix_product_closed_forms():
+    # all limbs 2^32 - 1: every entry is n (2^(32 na) - 1)^2 = n (2^(64 na) - 2^(32 na + 1) + 1)
+    n, na = 4, 5
+    full = np.full((n, n, na), 0xFFFFFFFF, dtype=np.uint32)
+    C = oracle.intmatmul_pyint(full, full)
+    want = n * (2 ** (64 * na) - 2 ** (32 * na + 1) + 1)
+    for i in range(n):
+        for j in range(n):
+            assert int.from_bytes(C[i, j].astype("<u4").tobytes(), "little") == want
+    # 1 x 1 reduces to the integer product; the identity matrix to a copy
+    A, B = _limbs(1, 7, 9901, 0), _limbs(1, 7, 9901, 1)
+    a16 = A[0, 0].astype("<u4").view("<u2")
+    b16 = B[0, 0].astype("<u4").view("<u2")
+    np.testing.assert_array_equal(oracle.intmatmul_pyint(A, B)[0, 0][:14], oracle.intmul_pyint(a16, b16))
+    eye = np.zeros((3, 3, 2), dtype=np.uint32)
+    for i in range(3):
+        eye[i, i, 0] = 1
+    M = _limbs(3, 2, 9902, 0)
+    np.testing.assert_array_equal(oracle.intmatmul_pyint(M, eye)[:, :, :2], M)
