@@ -253,7 +253,7 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
  * through page-locked staging, on one of `streams` streams (default priority).
  * Batches in flight overlap on the device (at most 2 per stream).  c == NULL: the
  * product is computed but not copied back.  The server owns one device buffer of
- * hbm_budget bytes (the arena) and its page-locked staging (128 MiB per batch in
+ * hbm_budget bytes (the arena) and its page-locked staging (32 MiB per batch in
  * flight, allocated at creation); the caller keeps a, b and c valid until the
  * request's id is reported.  One host thread drives a server.
  * Errors: NTT_EINVAL (arguments), NTT_ENOTPRIME / NTT_ENOROOT (kind 0 prime or length),

@@ -197,7 +197,7 @@ struct ntt_server {
   std::vector<hipStream_t> streams;
   unsigned next_stream = 0;
   size_t max_batch = 64;
-  size_t staging_cap = 128u << 20;  // operand + product bytes of one polynomial batch
+  size_t staging_cap = 32u << 20;  // operand + product bytes of one polynomial batch (smaller batches: shorter tails)
   std::vector<Staging> staging;
   std::vector<hipEvent_t> free_events;
   std::deque<Req> pending;
