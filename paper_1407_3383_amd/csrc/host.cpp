@@ -1778,21 +1778,19 @@ size_t polymatmul_workspace_bytes(uint64_t p, size_t n, size_t d) {
   return 2 * align256(n * n * N * sizeof(uint32_t));
 }
 
-int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
-                    size_t ws_bytes, void* hip_stream) {
-  try {
-    hipStream_t stream = (hipStream_t)hip_stream;
-    if (n == 0 || d == 0) return ok();
-    if (!A || !B || !C) return fail(NTT_EINVAL, "NULL matrix pointer");
-    if (!aligned_to(A, 4) || !aligned_to(B, 4) || !aligned_to(C, 4)) return fail(NTT_EINVAL, "misaligned pointer");
-    int rc = polymat_check(p, n, d);
-    if (rc) return rc;
+}  // extern "C"
+
+namespace {
+
+// The polynomial matrix product after its argument checks; reduce: the entries of A
+// and B are any 32-bit words, reduced modulo p as the first pass loads them.
+int polymat_run(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
+                hipStream_t stream, bool reduce) {
+  {
     const int L = polymat_log2(d);
     const size_t N = (size_t)1 << L, lc = 2 * d - 1, n2 = n * n;
-    const size_t need = polymatmul_workspace_bytes(p, n, d);
-    if (ws_bytes < need || !workspace) return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     ntt_plan* pl = nullptr;
-    rc = cached_plan(p, (uint32_t)L, &pl);
+    int rc = cached_plan(p, (uint32_t)L, &pl);
     if (rc) return rc;
     uint32_t* Ah = (uint32_t*)workspace;
     uint32_t* Bh = (uint32_t*)((unsigned char*)workspace + align256(n2 * N * sizeof(uint32_t)));
@@ -1812,6 +1810,7 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
       x.in_stride = d;
       x.out_stride = N;
       x.valid = d;
+      x.scale = reduce ? 2 : 0;
       PassJobs fwd;
       memset(&fwd, 0, sizeof(fwd));
       x.in = A;
@@ -1822,6 +1821,7 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
       fwd.j[fwd.n++] = x;
       HIP_TRY(launch_col_fwd_jobs(32, fwd, (int)pl->L1, (int)pl->L2, stream));
       PassArgs r = x;
+      r.scale = 0;
       r.in_stride = N;
       r.valid = N;
       r.in = Ah;
@@ -1831,8 +1831,9 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
       r.out = Bh;
       HIP_TRY(launch_row_fwd(32, r, (int)pl->L1, (int)pl->L2, stream));
     } else {
-      HIP_TRY(launch_copy_rows(Ah, N, N, (const uint32_t*)A, d, d, (uint32_t)n2, stream));
-      HIP_TRY(launch_copy_rows(Bh, N, N, (const uint32_t*)B, d, d, (uint32_t)n2, stream));
+      const uint32_t rp = reduce ? (uint32_t)p : 0u;
+      HIP_TRY(launch_copy_rows(Ah, N, N, (const uint32_t*)A, d, d, (uint32_t)n2, stream, rp));
+      HIP_TRY(launch_copy_rows(Bh, N, N, (const uint32_t*)B, d, d, (uint32_t)n2, stream, rp));
       LdsNttArgs t;
       memset(&t, 0, sizeof(t));
       t.in = Ah;
@@ -1874,6 +1875,7 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
     // inverse transforms of C's n^2 entries, the first 2d - 1 coefficients kept
     if (two_pass) {
       PassArgs v = x;
+      v.scale = 0;
       v.in = Ah;
       v.in_stride = N;
       v.out = Ah;
@@ -1899,7 +1901,27 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
       HIP_TRY(launch_lds_ntt(32, true, t, stream));
       HIP_TRY(launch_copy_rows((uint32_t*)C, lc, lc, Ah, N, lc, (uint32_t)n2, stream));
     }
-    return ok();
+    return NTT_OK;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d, void* C, void* workspace,
+                    size_t ws_bytes, void* hip_stream) {
+  try {
+    hipStream_t stream = (hipStream_t)hip_stream;
+    if (n == 0 || d == 0) return ok();
+    if (!A || !B || !C) return fail(NTT_EINVAL, "NULL matrix pointer");
+    if (!aligned_to(A, 4) || !aligned_to(B, 4) || !aligned_to(C, 4)) return fail(NTT_EINVAL, "misaligned pointer");
+    int rc = polymat_check(p, n, d);
+    if (rc) return rc;
+    const size_t need = polymatmul_workspace_bytes(p, n, d);
+    if (ws_bytes < need || !workspace) return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    rc = polymat_run(p, n, A, B, d, C, workspace, stream, false);
+    return rc ? rc : ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in polymatmul_modp");
   }
@@ -1911,7 +1933,7 @@ int polymatmul_modp(uint64_t p, size_t n, const void* A, const void* B, size_t d
 namespace {
 
 struct IntMatLayout {
-  size_t lc, npos, nblk, o_ar, o_br, o_r[3], o_pm, o_t, o_blk, total;
+  size_t lc, npos, nblk, o_r[3], o_pm, o_t, o_blk, total;
 };
 
 // n x n matrices of na-chunk integers: coefficients of C's entries are sums of n
@@ -1931,10 +1953,6 @@ IntMatLayout intmat_layout(size_t n, size_t na) {
   z.npos = 2 * na + 1;  // a sum of n products can carry one limb past 2 na
   z.nblk = (z.npos + crt_block_positions() - 1) / crt_block_positions();
   size_t off = 0;
-  z.o_ar = off;
-  off += align256(n2 * na * 4);
-  z.o_br = off;
-  off += align256(n2 * na * 4);
   for (int i = 0; i < 3; ++i) {
     z.o_r[i] = off;
     off += align256(n2 * z.lc * 4);
@@ -1973,16 +1991,11 @@ int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, u
     if (ws_bytes < z.total || !workspace)
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", z.total, ws_bytes);
     unsigned char* w = (unsigned char*)workspace;
-    uint32_t* ar = (uint32_t*)(w + z.o_ar);
-    uint32_t* br = (uint32_t*)(w + z.o_br);
     const size_t n2 = n * n;
-    const size_t pm_bytes = polymatmul_workspace_bytes(kIntPrimes[0], n, na);
     for (int i = 0; i < 3; ++i) {
-      // chunks of 32 bits exceed the primes: residues first, then the polynomial
-      // matrix product modulo this prime
-      HIP_TRY(launch_reduce_mod(A, ar, n2 * na, kIntPrimes[i], stream));
-      HIP_TRY(launch_reduce_mod(B, br, n2 * na, kIntPrimes[i], stream));
-      int rc = polymatmul_modp(kIntPrimes[i], n, ar, br, na, w + z.o_r[i], w + z.o_pm, pm_bytes, stream);
+      // the polynomial matrix product modulo this prime; chunks of 32 bits exceed the
+      // primes and are reduced as the first pass loads them
+      int rc = polymat_run(kIntPrimes[i], n, A, B, na, w + z.o_r[i], w + z.o_pm, stream, true);
       if (rc) return rc;
     }
     CrtArgs x;

@@ -157,8 +157,10 @@ struct MatArgs {
 };
 uint32_t freq_matmul_block(uint32_t n, uint64_t N);
 hipError_t launch_freq_matmul(const MatArgs& a, hipStream_t stream);
-// dst[r][t] = t < src_len ? src[r][t] : 0 for r < rows, t < dst_len.
+// dst[r][t] = t < src_len ? src[r][t] : 0 for r < rows, t < dst_len; reduce_p != 0
+// (< 2^31): every word reduced modulo reduce_p.
 hipError_t launch_copy_rows(uint32_t* dst, uint64_t dst_stride, uint64_t dst_len, const uint32_t* src,
-                            uint64_t src_stride, uint64_t src_len, uint32_t rows, hipStream_t stream);
+                            uint64_t src_stride, uint64_t src_len, uint32_t rows, hipStream_t stream,
+                            uint32_t reduce_p = 0);
 
 }  // namespace nttgpu

@@ -117,13 +117,20 @@ __global__ __launch_bounds__(kMatThreads) void freq_matmul_kernel(MatArgs M) {
   }
 }
 
+// p != 0: words reduced modulo p on the way (Function 8 with y = 1, psi = floor(2^32 / p),
+// gives [0, 2p) for any 32-bit word; one min finishes).
 __global__ void copy_rows_kernel(uint32_t* dst, uint64_t dst_stride, uint64_t dst_len, const uint32_t* src,
-                                 uint64_t src_stride, uint64_t src_len, uint32_t rows) {
+                                 uint64_t src_stride, uint64_t src_len, uint32_t rows, uint32_t p, uint32_t psi) {
   const uint64_t total = (uint64_t)rows * dst_len;
   for (uint64_t idx = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (uint64_t)gridDim.x * blockDim.x) {
     const uint64_t r = idx / dst_len, t = idx - r * dst_len;
-    dst[r * dst_stride + t] = t < src_len ? src[r * src_stride + t] : 0u;
+    uint32_t v = t < src_len ? src[r * src_stride + t] : 0u;
+    if (p) {
+      v = v - __umulhi(v, psi) * p;
+      v = min(v, v - p);
+    }
+    dst[r * dst_stride + t] = v;
   }
 }
 
@@ -132,7 +139,9 @@ __global__ void copy_rows_kernel(uint32_t* dst, uint64_t dst_stride, uint64_t ds
 uint32_t freq_matmul_block(uint32_t n, uint64_t N) {
   if (n == 0 || n > kMatMaxN) return 0;
   uint32_t kb = 256;
-  while (kb > 1 && (uint64_t)n * (n + 1) * kb > 8192) kb >>= 1;
+  // n (n + 1) KB words per operand, at most 8448 (33 KiB): two operands in 68 KiB of
+  // LDS, two workgroups per CU; KB = 8 at n = 32, 16 at n = 16 (measured best)
+  while (kb > 1 && (uint64_t)n * (n + 1) * kb > 8448) kb >>= 1;
   while ((uint64_t)kb > N) kb >>= 1;
   return kb;
 }
@@ -167,13 +176,16 @@ hipError_t launch_freq_matmul(const MatArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_copy_rows(uint32_t* dst, uint64_t dst_stride, uint64_t dst_len, const uint32_t* src,
-                            uint64_t src_stride, uint64_t src_len, uint32_t rows, hipStream_t stream) {
+                            uint64_t src_stride, uint64_t src_len, uint32_t rows, hipStream_t stream,
+                            uint32_t reduce_p) {
   const uint64_t total = (uint64_t)rows * dst_len;
   if (total == 0) return hipSuccess;
+  if (reduce_p >= (1u << 31)) return hipErrorInvalidValue;
+  const uint32_t psi = reduce_p ? (uint32_t)((1ull << 32) / reduce_p) : 0u;
   const uint64_t blocks = (total + 255) / 256;
   const uint32_t grid = (uint32_t)(blocks < 8192 ? blocks : 8192);
   hipLaunchKernelGGL(copy_rows_kernel, dim3(grid), dim3(256), 0, stream, dst, dst_stride, dst_len, src, src_stride,
-                     src_len, rows);
+                     src_len, rows, reduce_p, psi);
   return hipGetLastError();
 }
 
