@@ -579,19 +579,23 @@ DeviceCtx* device_ctx(int dev) {
 }
 
 // Cached plan for (current device, p, log2n) with the smallest generator.
-int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false) {
+// product: the plan's two-pass row length is the one tuned for products (whose row
+// pass is the fused row product); otherwise the one tuned for transforms.  Each kind
+// has its own cache key (p < 2^62, so bits 62 and 63 are free).
+int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false, bool product = true) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_EDEVICE, "hipGetDevice failed");
   DeviceCtx* c = device_ctx(dev);
   std::lock_guard<std::mutex> lk(c->mu);
-  auto key = std::make_pair(numeric ? (p | (1ull << 63)) : p, log2n);  // FP64 plans: p < 2^49, own key
+  const uint64_t tag = (numeric ? (1ull << 63) : 0) | (product ? 0 : (1ull << 62));
+  auto key = std::make_pair(p | tag, log2n);
   auto it = c->plans.find(key);
   if (it != c->plans.end()) {
     *out = it->second;
     return NTT_OK;
   }
   ntt_plan* pl = nullptr;
-  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, true, numeric);
+  int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, product, numeric);
   if (rc) return rc;
   c->plans[key] = pl;
   *out = pl;
@@ -1790,7 +1794,8 @@ int polymat_run(uint64_t p, size_t n, const void* A, const void* B, size_t d, vo
     const int L = polymat_log2(d);
     const size_t N = (size_t)1 << L, lc = 2 * d - 1, n2 = n * n;
     ntt_plan* pl = nullptr;
-    int rc = cached_plan(p, (uint32_t)L, &pl);
+    // plain transform passes (no fused row product): the transform-tuned row length
+    int rc = cached_plan(p, (uint32_t)L, &pl, false, false);
     if (rc) return rc;
     uint32_t* Ah = (uint32_t*)workspace;
     uint32_t* Bh = (uint32_t*)((unsigned char*)workspace + align256(n2 * N * sizeof(uint32_t)));
