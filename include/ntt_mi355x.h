@@ -323,6 +323,29 @@ size_t intmatmul32_workspace_bytes(size_t n, size_t na);
 int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, uint32_t* C, void* workspace,
                     size_t ws_bytes, void* hip_stream);
 
+/* Element-wise evaluation of one device primitive on n elements (a diagnostic for
+ * testing the arithmetic alone; every transform kernel uses these same forms).
+ * word: 32 or 64 (unsigned words, p < 2^31 or p < 2^62) or 0 (doubles, p < 2^49).
+ * x, y, ys, out: device arrays of the word type (ys: Shoup companions
+ * floor(y 2^W / p), op NTT_ARITH_SHOUP with unsigned words only; out: n words, 2n for
+ * the butterflies).  tw, tws: the butterflies' twiddle and its companion (the same in
+ * every lane); for doubles only tw is read.  Lazy ranges as in the kernels: unsigned
+ * 32-bit words lazy when p < 2^30, 64-bit words always, doubles when p < 2^48.
+ * Errors: NTT_EINVAL (op, word, p even or < 3, NULL or misaligned pointers),
+ * NTT_EUNSUPPORTED (p beyond the word's bound), NTT_EDEVICE. */
+#define NTT_ARITH_SHOUP 0 /* out = x y - floor(x ys / 2^W) p, in [0, 2p) for any word x (Function 8
+                             without its last line); doubles: Function 16, [0, 2p) */
+#define NTT_ARITH_MONT 1  /* out = x y 2^-W mod p, in (0, 2p), for x y < 2^W p (Function 13,
+                             subtractive form); doubles: Function 16, x y mod p in [0, 2p) */
+#define NTT_ARITH_RED1 2  /* out = x - p if x >= p else x (Function 2's min): [0, 2p) -> [0, p) */
+#define NTT_ARITH_RED2 3  /* out = x - 2p if x >= 2p else x: [0, 4p) -> [0, 2p) */
+#define NTT_ARITH_CT 4    /* forward butterfly: out[i] = X + w Y, out[n + i] = X - w Y mod p,
+                             lazy: X in [0, 4p) -> [0, 4p); else X in [0, 2p) -> [0, 2p) */
+#define NTT_ARITH_GS 5    /* inverse butterfly: out[i] = X + Y, out[n + i] = (X - Y) w mod p,
+                             lazy: [0, 2p) -> [0, 2p); else [0, p) -> [0, p) */
+int ntt_arith_apply(int op, int word, uint64_t p, const void* x, const void* y, const void* ys, uint64_t tw,
+                    uint64_t tws, void* out, size_t n, void* hip_stream);
+
 /* Products mod p with residues held in doubles (section 3: modular arithmetic over
  * numeric types; products by Function 16, the FMA product, sums by Function 17's
  * compare-and-subtract), in the same fused one-workgroup kernels as polymul_modp_batch.

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip",
-           "kernels_matrix.hip"]
+           "kernels_matrix.hip", "kernels_arith.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

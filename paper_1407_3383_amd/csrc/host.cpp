@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/ntt_mi355x.h"
+#include "arith_apply.hpp"
 #include "kernels.hpp"
 
 using namespace nttgpu;
@@ -2184,6 +2185,47 @@ int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, 
     return ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in polymul_f64_batch");
+  }
+}
+
+}  // extern "C"
+
+// ============================================================================ primitives alone
+extern "C" {
+
+int ntt_arith_apply(int op, int word, uint64_t p, const void* x, const void* y, const void* ys, uint64_t tw,
+                    uint64_t tws, void* out, size_t n, void* hip_stream) {
+  try {
+    if (op < NTT_ARITH_SHOUP || op > NTT_ARITH_GS) return fail(NTT_EINVAL, "unknown primitive %d", op);
+    if (word != 32 && word != 64 && word != 0) return fail(NTT_EINVAL, "word must be 32, 64 or 0 (doubles)");
+    if (p < 3 || !(p & 1)) return fail(NTT_EINVAL, "modulus must be odd and at least 3");
+    const uint64_t bound = word == 32 ? (1ull << 31) : word == 64 ? kMaxModulus : (1ull << 49);
+    if (p >= bound) return fail(NTT_EUNSUPPORTED, "modulus %llu beyond the word's bound", (unsigned long long)p);
+    if (n == 0) return ok();
+    const bool needs_y = op != NTT_ARITH_RED1 && op != NTT_ARITH_RED2;
+    if (!x || !out || (needs_y && !y) || (op == NTT_ARITH_SHOUP && word != 0 && !ys))
+      return fail(NTT_EINVAL, "NULL array");
+    const size_t esz = word == 32 ? 4 : 8;
+    if (!aligned_to(x, esz) || !aligned_to(out, esz) || (y && !aligned_to(y, esz)) || (ys && !aligned_to(ys, esz)))
+      return fail(NTT_EINVAL, "arrays must be %zu-byte aligned", esz);
+    ArithArgs a;
+    memset(&a, 0, sizeof(a));
+    a.x = x;
+    a.y = y;
+    a.ys = ys;
+    a.out = out;
+    a.n = n;
+    a.p = p;
+    a.pinv = word ? inv_pow2_word(p, word) : 0;
+    a.tw = tw;
+    a.tws = tws;
+    a.twd = (double)tw;
+    a.op = op;
+    a.word = word;
+    HIP_TRY(launch_arith_apply(a, (hipStream_t)hip_stream));
+    return ok();
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in ntt_arith_apply");
   }
 }
 

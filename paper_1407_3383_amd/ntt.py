@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libntt_mi355x.so")
 # NTT_TUNE_FILE names another file, or (empty) none.
 TUNE_FILE = os.path.join(_HERE, "tuning", "gfx950.txt")
 
+NTT_ARITH_SHOUP, NTT_ARITH_MONT, NTT_ARITH_RED1, NTT_ARITH_RED2, NTT_ARITH_CT, NTT_ARITH_GS = range(6)
 NTT_OK = 0
 NTT_EINVAL = -1
 NTT_ENOTPRIME = -2
@@ -45,7 +46,7 @@ EXPORTS = (
     "polymul_batch_launch_workspace_bytes", "polymul_batch_launch", "polymul_batch_destroy",
     "intmul_workspace_bytes", "intmul_crt", "intmul_chunk_bits", "intmul32_workspace_bytes", "intmul_crt32",
     "polymatmul_workspace_bytes", "polymatmul_modp", "polymul_f64_batch_workspace_bytes", "polymul_f64_batch",
-    "polymul_f64_batch_create", "intmatmul32_workspace_bytes", "intmatmul_crt32",
+    "polymul_f64_batch_create", "intmatmul32_workspace_bytes", "intmatmul_crt32", "ntt_arith_apply",
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
@@ -117,6 +118,7 @@ def load(path: str = LIB_PATH):
         "polymul_f64_batch_create": (ci, [ctypes.POINTER(vp), ctypes.POINTER(PolymulDesc), sz]),
         "intmatmul32_workspace_bytes": (sz, [sz, sz]),
         "intmatmul_crt32": (ci, [sz, vp, vp, sz, vp, vp, sz, vp]),
+        "ntt_arith_apply": (ci, [ctypes.c_int, ctypes.c_int, u64, vp, vp, vp, u64, u64, vp, sz, vp]),
         "ntt_tune_set": (ci, [ctypes.c_char_p, ctypes.c_int64]),
         "ntt_tune_get": (ci, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]),
         "ntt_tune_clear": (ci, []),

@@ -196,3 +196,15 @@ def test_intmatmul_argument_errors_and_sizes(lib):
     # the section's table: 32 x 32 entries of 2^15 chunks fit (32 2^15 (2^32 - 1)^2 < p1 p2 p3)
     assert lib.intmatmul32_workspace_bytes(32, 1 << 15) > 3 * 32 * 32 * ((1 << 16) - 1) * 4
     assert lib.intmatmul32_workspace_bytes(64, 1 << 17) == 0
+
+
+def test_arith_apply_argument_errors(lib):
+    one = ctypes.c_void_p(16)
+    assert lib.ntt_arith_apply(9, 32, 998244353, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EINVAL
+    assert lib.ntt_arith_apply(0, 16, 998244353, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EINVAL
+    assert lib.ntt_arith_apply(0, 32, 998244352, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EINVAL
+    assert lib.ntt_arith_apply(0, 32, 2 ** 31 + 11, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.ntt_arith_apply(0, 0, 63 * 2 ** 44 + 1, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.ntt_arith_apply(0, 32, 998244353, one, one, None, 0, 0, one, 8, None) == ntt.NTT_EINVAL
+    assert lib.ntt_arith_apply(2, 64, 998244353, ctypes.c_void_p(20), None, None, 0, 0, one, 8, None) == ntt.NTT_EINVAL
+    assert lib.ntt_arith_apply(2, 64, 998244353, one, None, None, 0, 0, one, 0, None) == ntt.NTT_OK
