@@ -145,3 +145,17 @@ def test_native_server_small_budget_and_refusal():
     with pytest.raises(ValueError):
         tiny.run(_requests(2, rate=1000.0, lo=14.0, hi=14.5, seed=7))
     tiny.close()
+
+
+def test_native_server_without_copy_back():
+    """Requests whose products stay on the device (c = NULL): every request completes
+    and the server ends empty."""
+    torch_cuda()
+    reqs = _requests(60, rate=1e6, lo=8.0, hi=14.0, seed=8)
+    srv = serve.NativeServer(budget_bytes=128 << 20, streams=4, max_batch=16, keep_results=False)
+    srv.run(reqs, realtime=False)
+    assert sorted(r.rid for r in srv.completed) == sorted(r.rid for r in reqs)
+    assert all(r.result is None for r in srv.completed)
+    st = srv.stats()
+    assert st["pending"] == 0 and st["inflight"] == 0 and st["arena_used"] == 0
+    srv.close()
