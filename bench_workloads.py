@@ -39,6 +39,19 @@ def _time(fn, stream, steps, warmup):
     return wall_ms, e0.elapsed_time(e1) / steps
 
 
+def _alu(ops, ms):
+    """Integer-VALU roofline of a step that needs `ops` lane operations."""
+    achieved = ops / (ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
+            "unit": "Tops/s (32-bit integer lane operations)", "frac": round(achieved / ALU_PEAK_TOPS, 4)}
+
+
+def _hbm(nbytes, ms):
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"algorithmic_bytes_per_step": int(nbytes), "achieved_GBps": round(gbps, 1),
+            "frac": round(gbps / HBM_PEAK_GBPS, 4)}
+
+
 def _line(metric, value, unit, ms, steps, warmup, config, extra):
     out = {"metric": metric, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": steps,
            "warmup": warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
@@ -105,8 +118,7 @@ def run(name, args):
                       "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
                               "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                               "pass_bytes_per_step": 8 * n * 4},
-                      "alu": {"achieved_Tops": round(bfly * OPS_PER_BFLY / (ms * 1e-3) / 1e12, 3),
-                              "peak_Tops": round(ALU_PEAK_TOPS, 3)}})
+                      "alu": _alu(bfly * OPS_PER_BFLY, ms)})
     if name == "intmul":
         a, b = inputs.intmul_inputs()
         da, db = ntt.to_device(a), ntt.to_device(b)
@@ -128,8 +140,7 @@ def run(name, args):
                      {"workload": "product of two 2^21-limb (16-bit) integers, primes 998244353, 469762049, 167772161, transform length 2^22"},
                      {"ms_per_product": round(ms, 4),
                       "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 2)},
-                      "alu": {"achieved_Tops": round(bfly * OPS_PER_BFLY / (ms * 1e-3) / 1e12, 3),
-                              "peak_Tops": round(ALU_PEAK_TOPS, 3)}})
+                      "alu": _alu(bfly * OPS_PER_BFLY, ms)})
     if name == "intmul32":
         # the same two integers as the integer-product configuration, in 32-bit chunks
         # (section 5.3's choice of h for these primes): transform length 2^21
@@ -153,7 +164,9 @@ def run(name, args):
                      bfly / (ms * 1e-3) / 1e9, "Gbfly/s", ms, steps, 2,
                      {"workload": "product of the same two 2^25-bit integers as 2^20 chunks of 32 bits (h = 32 by "
                                   "the chunk-size rule), primes 998244353, 469762049, 167772161, transform length 2^21"},
-                     {"ms_per_product": round(ms, 4), "chunk_bits": ntt.intmul_chunk_bits(a.size, b.size)})
+                     {"ms_per_product": round(ms, 4), "chunk_bits": ntt.intmul_chunk_bits(a.size, b.size),
+                      "alu": _alu(bfly * OPS_PER_BFLY, ms),
+                      "hbm": _hbm(2 * a32.size * 4 + (a32.size + b32.size) * 4, ms)})
     if name == "tft":
         # TFT truncation at sub-problem granularity: 1024 products mod 2013265921 of
         # operands of length 20000 (lc = 39999 <= 3 * 2^14: 3 of the 4 sub-problems of the
@@ -222,6 +235,7 @@ def run_polymatrix(args):
         macs = n ** 3 * N
         alg = (2 * n * n * d + n * n * (2 * d - 1)) * 4
         rows[n] = {"ms": round(kms, 4), "Gbfly_per_s": round(bfly / (kms * 1e-3) / 1e9, 1),
+                   "alu": _alu(bfly * OPS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
                    "Gmac_per_s": round(macs / (kms * 1e-3) / 1e9, 1),
                    "algorithmic_GBps": round(alg / (kms * 1e-3) / 1e9, 1),
                    "paper_cpu_s": PAPER_POLYMATRIX_S.get(n)}
@@ -405,7 +419,12 @@ def run_intmatrix(args):
             ntt._check(L.intmatmul_crt32(n, ntt._ptr(dA), ntt._ptr(dB), na, ntt._ptr(dC), ntt._ptr(ws), ws.numel(),
                                          ntt._stream(stream)), "intmatmul_crt32")
         _, kms = _time(step, stream, max(args.steps, 10), 2)
-        rows[n] = {"ms": round(kms, 4), "paper_cpu_s": PAPER_INTMATRIX_S.get(n)}
+        N = 1 << 16
+        bfly = 3 * 3 * n * n * (N // 2) * 16
+        macs = 3 * n ** 3 * N
+        alg = (2 * n * n * na + n * n * (2 * na + 1)) * 4
+        rows[n] = {"ms": round(kms, 4), "alu": _alu(bfly * OPS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
+                   "paper_cpu_s": PAPER_INTMATRIX_S.get(n)}
         _log("intmatrix n=%d: %.4f ms" % (n, kms))
         del dA, dB, dC, ws
     top = rows[max(rows)]
