@@ -52,6 +52,8 @@ EXACT = [
     (469762049, 1, 1), (469762049, 2, 2), (469762049, 1, 4096), (469762049, 3, 100), (998244353, 4, 257),
     (2013265921, 5, 300), (7340033, 8, 64), (469762049, 13, 40), (469762049, 64, 8), (469762049, 33, 30),
     (469762049, 9, 700), (2013265921, 2, 4097), (998244353, 2, 5000), (469762049, 17, 3),
+    # n = 32: the section's largest matrices, exact at small degrees (31-bit and small primes)
+    (469762049, 32, 40), (2013265921, 32, 9), (7340033, 32, 3), (998244353, 32, 2), (469762049, 32, 1),
 ]
 
 
