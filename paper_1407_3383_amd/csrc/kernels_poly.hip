@@ -38,10 +38,13 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
   const int d = (int)it.log2n - M;
   const int nsub = 1 << d;
   const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
+  // TFT truncation (d = 2): lc > 2S, so lam = ceil(lc / S) is 3 or 4; with 3 the fourth
+  // partial is completed from the zero coefficients c_k, k >= 3S (plan constants tft2)
+  const int lam = (d == 2 && lc <= 3 * (uint64_t)S) ? 3 : nsub;
   T P0[(PM == 0 && MAXD > 0) ? EPT : 1], P1[(PM == 0 && MAXD > 1) ? EPT : 1], P2[(PM == 0 && MAXD > 1) ? EPT : 1];
   T* const sv2[2] = {sa, sb};
 
-  for (int h = 0; h < nsub; ++h) {
+  for (int h = 0; h < lam; ++h) {
     // Fold of both operands (indices >= la, lb read as 0); the Montgomery scale
     // 2^bits/N is applied to b so that the entry-wise Montgomery product yields
     // a^ b^ / N.  The terms k = 0, 1 of every position of the thread are requested
@@ -134,7 +137,7 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
       inv_lds_ct<T, LAZY, NT, M>(ar, sa, d, (uint32_t)h, twi);
     }
     const int tr = opaque_tid();
-    if (h + 1 < nsub) {
+    if (h + 1 < lam) {
       if constexpr (MAXD > 0) {
 #pragma unroll
         for (int k = 0; k < EPT; ++k) {  // fully unrolled: P0..P2 stay in registers
@@ -168,8 +171,11 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
           q2[k] = (MAXD > 1) ? P2[k] : (T)0;
         }
       }
-      // recombination twiddles, loaded before any output store
+      // recombination twiddles and completion factors, loaded before any output store
       const TwPair<T> w1 = uni(ldtw<T>(twi + 1)), w2 = uni(ldtw<T>(twi + 2)), w3 = uni(ldtw<T>(twi + 3));
+      TwPair<T> kf[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) kf[i] = uni(ldtw<T>(gconst<TwPair<T>>((const void*)&pc->tft2[i])));
 #pragma unroll
       for (int k = 0; k < EPT; ++k) {
         const int j = tr + k * NT;
@@ -187,7 +193,17 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
             }
           } else {
             if constexpr (MAXD > 1) {
-              T x0 = q0[k], x1 = q1[k], x2 = q2[k], x3 = v0;
+              T x0 = q0[k], x1 = q1[k], x2, x3;
+              if (lam == 4) {
+                x2 = q2[k];
+                x3 = v0;
+              } else {  // x3 = k0 x0 + k1 x1 + k2 x2: the partial that makes c_3 vanish
+                x2 = v0;
+                const T s0 = ar.red1(ar.shoup_u(x0, kf[0].w, kf[0].ws));
+                const T s1 = ar.red1(ar.shoup_u(x1, kf[1].w, kf[1].ws));
+                const T s2 = ar.red1(ar.shoup_u(x2, kf[2].w, kf[2].ws));
+                x3 = ar.red1(ar.red1(s0 + s1) + s2);
+              }
               gs_bfly<LAZY, true>(ar, x0, x1, w2);
               gs_bfly<LAZY, true>(ar, x2, x3, w3);
               gs_bfly<LAZY, true>(ar, x0, x2, w1);

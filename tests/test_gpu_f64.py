@@ -15,7 +15,9 @@ pytestmark = pytest.mark.gpu
 P48 = numtheory.largest_prime_below(48, 20)   # lazy ranges (operands below 4p)
 P49 = numtheory.largest_prime_below(49, 20)   # operands below 2p
 SHAPES = [(1, 1), (2, 3), (100, 37), (1000, 1000), (4096, 4096), (5000, 11), (3000, 9000), (1 << 14, 1 << 14),
-          (16383, 2)]
+          (16383, 2),
+          # 2^15-point products with lc <= 3 * 2^13: 3 of 4 sub-problems (TFT truncation)
+          (8193, 8193), (12288, 12289), (20000, 2)]
 
 
 def _f64(x, torch):

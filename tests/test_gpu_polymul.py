@@ -122,3 +122,22 @@ def test_fused_truncated_products(la, lb):
     got = ntt.polymul_batch(pairs, [p] * 3)
     for k in range(3):
         assert_equal_u(ntt.to_numpy(got[k]), want[k], "fused truncated product %d" % k)
+
+
+# The same truncation in the 64-bit-word fused kernel (2^15-point products, sub-problems
+# of 2^13): lc <= 3 * 2^13 computes 3 of the 4 sub-problems
+@pytest.mark.parametrize("la,lb", [(8193, 8193), (10000, 9000), (12288, 12288), (12289, 12288), (12289, 12289),
+                                   (20000, 2), (2, 24000)])
+def test_fused_truncated_products_64bit(la, lb):
+    torch_cuda()
+    p = P62
+    pairs, want = [], []
+    for k in range(2):
+        a = inputs.residues(p, la, inputs.CFG_TEST, 1750 + k, 0)
+        b = inputs.residues(p, lb, inputs.CFG_TEST, 1750 + k, 1)
+        pairs.append((ntt.to_device(a), ntt.to_device(b)))
+        want.append(oracle.polymul_ntt(a, b, p))
+    say("64-bit fused batch truncated products la=%d lb=%d" % (la, lb))
+    got = ntt.polymul_batch(pairs, [p] * 2)
+    for k in range(2):
+        assert_equal_u(ntt.to_numpy(got[k]), want[k], "64-bit fused truncated product %d" % k)
