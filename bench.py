@@ -101,7 +101,7 @@ def main() -> int:
     ap.add_argument("--matrix-n", type=int, default=0, help="polymatrix, intmatrix: one matrix size only (default 1 .. 32)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the products shard trivially across GPUs; see the design notes).", file=sys.stderr)
         return 2
 
