@@ -93,3 +93,29 @@ def test_random_integer_products(seed):
         B = int.from_bytes(b32.astype("<u4").tobytes(), "little")
         want32 = np.frombuffer((A * B).to_bytes(4 * (ma + mb), "little"), dtype="<u4")
         assert_equal_u(got32, want32, "intmul32 seed %d %dx%d" % (seed, ma, mb))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_matrix_products(seed):
+    torch = torch_cuda()
+    g = np.random.default_rng(34000 + seed)
+    for k in range(3):
+        n = int(g.integers(1, 65))
+        d = max(1, int(2 ** g.uniform(0, 7 if n > 16 else 10)))
+        p = [469762049, 998244353, 2013265921, 7340033][int(g.integers(4))]
+        A = inputs.residues(p, n * n * d, inputs.CFG_TEST, 34000 + 10 * seed + k, 0).reshape(n, n, d)
+        B = inputs.residues(p, n * n * d, inputs.CFG_TEST, 34000 + 10 * seed + k, 1).reshape(n, n, d)
+        say("random polymatmul seed %d: p=%d n=%d d=%d" % (seed, p, n, d))
+        C = ntt.polymatmul(ntt.to_device(A.reshape(-1)).reshape(n, n, d), ntt.to_device(B.reshape(-1)).reshape(n, n, d), p)
+        torch.cuda.synchronize()
+        assert_equal_u(ntt.to_numpy(C.reshape(-1)), oracle.polymatmul(A, B, p).reshape(-1),
+                       "polymatmul seed %d p=%d n=%d d=%d" % (seed, p, n, d))
+    n = int(g.integers(1, 13))
+    na = max(1, int(2 ** g.uniform(0, 9)))
+    A = inputs.limbs32(n * n * na, inputs.CFG_TEST, 34500 + seed, 0).reshape(n, n, na)
+    B = inputs.limbs32(n * n * na, inputs.CFG_TEST, 34500 + seed, 1).reshape(n, n, na)
+    say("random intmatmul seed %d: n=%d na=%d" % (seed, n, na))
+    C = ntt.intmatmul32(ntt.to_device(A.reshape(-1)).reshape(n, n, na), ntt.to_device(B.reshape(-1)).reshape(n, n, na))
+    torch.cuda.synchronize()
+    assert_equal_u(ntt.to_numpy(C.reshape(-1)).astype(np.uint32), oracle.intmatmul_pyint(A, B).reshape(-1),
+                   "intmatmul seed %d n=%d na=%d" % (seed, n, na))
