@@ -291,6 +291,9 @@ def run_serve(args):
     back = Server(budget, streams=4, max_batch=64, keep_results=True)
     wall_back = back.run(make([0.0] * m), realtime=False)
     back.close()
+    pin = Server(budget, streams=4, max_batch=64, keep_results=True, pinned_results=True)
+    wall_pin = pin.run(make([0.0] * m), realtime=False)
+    pin.close()
     # native loop on the same m requests (the comparisons' own reference)
     sub = Server(budget, streams=4, max_batch=64, keep_results=False)
     wall_sub = sub.run(make([0.0] * m), realtime=False)
@@ -305,6 +308,8 @@ def run_serve(args):
            "first_%d_requests" % m: {
                "native_saturated": {"requests_per_s": round(m / wall_sub, 2), **serve.latency_stats(sub.completed)},
                "native_with_copy_back": {"requests_per_s": round(m / wall_back, 2), **serve.latency_stats(back.completed)},
+               "native_with_copy_back_to_pinned": {"requests_per_s": round(m / wall_pin, 2),
+                                                   **serve.latency_stats(pin.completed)},
                "python_loop_saturated": {"requests_per_s": round(m / pywall, 2), **serve.latency_stats(pysat.completed)}}}
     levels = {}
     for frac in (0.5, 0.8, 0.95):

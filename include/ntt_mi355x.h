@@ -252,7 +252,8 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
  * an integer product one intmul_crt call, each batch with one upload and one download
  * through page-locked staging, on one of `streams` streams (default priority).
  * Batches in flight overlap on the device (at most 2 per stream).  c == NULL: the
- * product is computed but not copied back.  The server owns one device buffer of
+ * product is computed but not copied back; c in page-locked host memory (hipHostMalloc,
+ * torch pin_memory): the product is copied there directly by DMA, without staging.  The server owns one device buffer of
  * hbm_budget bytes (the arena) and its page-locked staging (32 MiB per batch in
  * flight, allocated at creation); the caller keeps a, b and c valid until the
  * request's id is reported.  One host thread drives a server.

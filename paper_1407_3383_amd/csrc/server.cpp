@@ -43,6 +43,7 @@ struct Req {
   const void* b;
   size_t lb;
   void* c;
+  bool direct;  // c is page-locked: the product goes there by DMA, not through staging
   size_t esz() const { return kind == 1 ? 2 : (p < (1ull << 31) ? 4 : 8); }
   size_t out_elems() const { return kind == 1 ? (la + lb + 1) / 2 : la + lb - 1; }
   size_t out_esz() const { return kind == 1 ? 4 : esz(); }
@@ -209,6 +210,18 @@ struct ntt_server {
 
 namespace {
 
+// Whether host memory at ptr is page-locked (hipHostMalloc, torch pin_memory): then
+// a device-to-host copy can land there directly.  The query's error for pageable
+// memory is cleared so that no later hipGetLastError reports it.
+bool page_locked(const void* ptr) {
+  if (!ptr) return false;
+  hipPointerAttribute_t at;
+  memset(&at, 0, sizeof(at));
+  const hipError_t e = hipPointerGetAttributes(&at, ptr);
+  (void)hipGetLastError();
+  return e == hipSuccess && at.type == hipMemoryTypeHost;
+}
+
 int acquire_staging(ntt_server* s, size_t bytes, int* idx) {
   for (size_t i = 0; i < s->staging.size(); ++i) {
     if (!s->staging[i].busy && s->staging[i].cap >= bytes) {
@@ -288,10 +301,21 @@ int launch(ntt_server* s, Batch& bt) {
     rc = polymul_modp_batch(d.data(), d.size(), bt.ws_bytes ? dev + bt.ws_off : nullptr, bt.ws_bytes, st);
   }
   if (rc) return rc;
-  bool want = false;
-  for (const Req& r : bt.reqs) want |= r.c != nullptr;
-  if (want && hipMemcpyAsync(host + bt.op_bytes, dev + bt.op_bytes, bt.out_bytes, hipMemcpyDeviceToHost, st) !=
-                  hipSuccess)
+  // products: page-locked destinations by DMA each, the others through staging (one copy
+  // of the whole product region)
+  bool staged = false;
+  for (size_t i = 0; i < bt.reqs.size(); ++i) {
+    const Req& r = bt.reqs[i];
+    if (!r.c) continue;
+    if (!r.direct) {
+      staged = true;
+      continue;
+    }
+    if (hipMemcpyAsync(r.c, dev + bt.off_c[i], r.out_elems() * r.out_esz(), hipMemcpyDeviceToHost, st) != hipSuccess)
+      return NTT_EDEVICE;
+  }
+  if (staged && hipMemcpyAsync(host + bt.op_bytes, dev + bt.op_bytes, bt.out_bytes, hipMemcpyDeviceToHost, st) !=
+                    hipSuccess)
     return NTT_EDEVICE;
   if (!s->free_events.empty()) {
     bt.ev = s->free_events.back();
@@ -377,7 +401,7 @@ int ntt_server_submit(ntt_server* s, uint64_t id, int kind, uint64_t p, const vo
   } else if (la + lb - 1 > ((size_t)1 << 23)) {
     return NTT_EINVAL;
   }
-  Req r{id, kind, p, a, la, b, lb, c};
+  Req r{id, kind, p, a, la, b, lb, c, page_locked(c)};
   Batch one;
   one.reqs.push_back(r);
   layout(one);
@@ -402,7 +426,7 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
     std::vector<CopyPool::Copy> cp;
     for (size_t i = 0; i < it->reqs.size(); ++i) {
       const Req& r = it->reqs[i];
-      if (r.c) cp.push_back(CopyPool::Copy{r.c, host + it->off_c[i], r.out_elems() * r.out_esz()});
+      if (r.c && !r.direct) cp.push_back(CopyPool::Copy{r.c, host + it->off_c[i], r.out_elems() * r.out_esz()});
       done_ids[(*ndone)++] = r.id;
     }
     s->pool->copy(cp);

@@ -309,9 +309,13 @@ class NativeServer:
     and completion run in native code; this class only feeds arrivals and collects
     completions.  Results always come back to host arrays (Request.result)."""
 
-    def __init__(self, budget_bytes: int, streams: int = 4, max_batch: int = 64, keep_results: bool = True):
+    def __init__(self, budget_bytes: int, streams: int = 4, max_batch: int = 64, keep_results: bool = True,
+                 pinned_results: bool = False):
+        """pinned_results: result arrays in page-locked memory, which the server fills by
+        DMA directly (no staging copy)."""
         import torch
         self.torch = torch
+        self.pinned_results = pinned_results
         L = ntt.load()
         h = ctypes.c_void_p()
         ntt._check(L.ntt_server_create(ctypes.byref(h), budget_bytes, streams, max_batch), "ntt_server_create")
@@ -338,8 +342,13 @@ class NativeServer:
             dt = np.uint32 if (r.kind == "int" or r.p < (1 << 31)) else np.uint64
             # result buffers touched before the run, so that no page is first touched
             # by the copy-back inside it
-            r.result = np.zeros(n, dtype=dt) if self.keep_results else None
-            if r.result is not None:
+            r.result = None
+            if self.keep_results and self.pinned_results:
+                tdt = self.torch.int32 if dt == np.uint32 else self.torch.int64
+                r._pinned = self.torch.empty(n, dtype=tdt, pin_memory=True)
+                r.result = r._pinned.numpy().view(dt)
+            elif self.keep_results:
+                r.result = np.zeros(n, dtype=dt)
                 r.result.fill(1)
             r.a = np.ascontiguousarray(r.a)
             r.b = np.ascontiguousarray(r.b)

@@ -159,3 +159,26 @@ def test_native_server_without_copy_back():
     st = srv.stats()
     assert st["pending"] == 0 and st["inflight"] == 0 and st["arena_used"] == 0
     srv.close()
+
+
+def test_native_server_pinned_results():
+    """Results in page-locked host memory are filled by DMA directly (no staging copy):
+    the same values as the request served alone and as the oracle."""
+    torch_cuda()
+    polys = _requests(40, rate=1e6, lo=8.0, hi=15.0, seed=9)
+    ints = []
+    for k in range(4):
+        n = 300 + 2000 * k
+        a = inputs.limbs16(n, inputs.CFG_SERVE, 7100 + k, 0)
+        b = inputs.limbs16(n // 3 + 1, inputs.CFG_SERVE, 7100 + k, 1)
+        ints.append(serve.Request(81000 + k, 0, a, b, arrival=0.0, kind="int"))
+    srv = serve.NativeServer(budget_bytes=256 << 20, streams=4, max_batch=16, pinned_results=True)
+    srv.run(polys + ints, realtime=False)
+    assert len(srv.completed) == len(polys) + len(ints)
+    for r in polys:
+        assert_equal_u(r.result, _alone(r), "pinned native request %d mix vs alone" % r.rid)
+    for r in polys[:6]:
+        assert_equal_u(r.result, oracle.polymul_ntt(r.a, r.b, r.p), "pinned native request %d vs oracle" % r.rid)
+    for r in ints:
+        assert_equal_u(r.result, oracle.intmul_pyint(r.a, r.b), "pinned integer request %d vs Python int" % r.rid)
+    srv.close()
