@@ -84,11 +84,10 @@ def test_sixty_two_bit_prime_rule():
     assert sympy.n_order(w, p) == 1 << 21
 
 
-@pytest.mark.parametrize("p", [998244353, 2013265921, 469762049, 167772161, 97, 257, 65537])
-@pytest.mark.parametrize("m", [8, 16, 32])
+# Montgomery's representation needs p < 2^m: only those pairs
+@pytest.mark.parametrize("p,m", [(p, m) for p in (998244353, 2013265921, 469762049, 167772161, 97, 257, 65537)
+                                 for m in (8, 16, 32) if p < (1 << m)])
 def test_montgomery_constants_identity(p, m):
-    if p >= (1 << m):
-        pytest.skip("Montgomery needs p < 2^m")
     rho, chi = nt.montgomery_constants(p, m)
     assert rho * (1 << m) - chi * p == 1
     assert 0 < chi < (1 << m) and 0 < rho < p
