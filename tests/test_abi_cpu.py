@@ -77,11 +77,12 @@ def test_plan_argument_errors(lib):
     assert _plan_rc(lib, 2, 0, 1) == ntt.NTT_EUNSUPPORTED
     assert _plan_rc(lib, 1 << 62, 0, 4) == ntt.NTT_EUNSUPPORTED
     assert _plan_rc(lib, 998244353, 0, 24) == ntt.NTT_ENOROOT      # 2-adic order 23
+    assert lib.ntt_last_error() == b"2^24 does not divide p - 1 (2-adic order 23)"
     assert _plan_rc(lib, 998244353, 0, 27) == ntt.NTT_EUNSUPPORTED  # beyond 26
     assert _plan_rc(lib, 998244353, 2, 4) == ntt.NTT_ENOROOT       # 2 is not a generator
     assert _plan_rc(lib, 998244353, 0, 4, 0x80) == ntt.NTT_EINVAL
     assert lib.ntt_plan_create(None, 998244353, 0, 4, 0, None) == ntt.NTT_EINVAL
-    assert b"2-adic" in lib.ntt_last_error() or True
+    assert lib.ntt_last_error() != b""
 
 
 def test_polymul_argument_errors(lib):
