@@ -145,6 +145,23 @@ size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb);
 int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
                  size_t ws_bytes, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same product as polymul_modp,
+ * with the same arguments minus the workspace, which is instead a fixed array of
+ * NTT_NOALLOC_SCRATCH_BYTES in device memory that the library holds on every device
+ * it runs on until the process ends.  The call allocates nothing (no hipMalloc, no
+ * host staging) and so creates no plan: the plan of (p, N) must already be cached on
+ * the current device, which any earlier polymul_modp call with the same modulus and
+ * transform length does.  Nothing in the array needs to start at zero; every call
+ * writes what it reads.  All calls on one device share its array: calls whose work
+ * can overlap on the device (different streams, or host threads racing on one) race
+ * on it and give wrong results; serialize them on one stream.
+ * Errors: as polymul_modp, plus NTT_EINVAL when the plan is not cached yet and
+ * NTT_ENOMEM when the product needs more scratch than the array holds (two-pass
+ * products: 2 N words, i.e. N <= 2^22 for 32-bit words and N <= 2^21 for 64-bit). */
+#define NTT_NOALLOC_SCRATCH_BYTES (32u << 20)
+int polymul_modp_noalloc(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* hip_stream);
+
 /* Device scratch for polymul_modp_batch on these descriptors. */
 size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
 

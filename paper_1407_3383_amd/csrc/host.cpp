@@ -583,7 +583,9 @@ DeviceCtx* device_ctx(int dev) {
 // product: the plan's two-pass row length is the one tuned for products (whose row
 // pass is the fused row product); otherwise the one tuned for transforms.  Each kind
 // has its own cache key (p < 2^62, so bits 62 and 63 are free).
-int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false, bool product = true) {
+// create = false: only look the plan up (callers that must not allocate).
+int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false, bool product = true,
+                bool create = true) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_EDEVICE, "hipGetDevice failed");
   DeviceCtx* c = device_ctx(dev);
@@ -595,6 +597,9 @@ int cached_plan(uint64_t p, uint32_t log2n, ntt_plan** out, bool numeric = false
     *out = it->second;
     return NTT_OK;
   }
+  if (!create)
+    return fail(NTT_EINVAL, "no cached plan for p = %llu and transform length 2^%u on device %d: one polymul_modp "
+                "call with this modulus and transform length creates it", (unsigned long long)p, log2n, dev);
   ntt_plan* pl = nullptr;
   int rc = create_plan(&pl, p, 0, log2n, NTT_BITREV_OUT | NTT_BITREV_IN, product, numeric);
   if (rc) return rc;
@@ -1033,22 +1038,11 @@ size_t batch_scratch(const std::vector<ProductShape>& shapes, int cus, size_t* n
   return need;
 }
 
-}  // namespace
-
-extern "C" {
-
-size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
-  if (la == 0 || lb == 0) return 0;
-  ProductShape s;
-  if (shape_of(p, la, lb, &s)) return 0;
-  single_path(&s);
-  return single_product_ws(s, current_cus());
-}
-
-int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
-                 size_t ws_bytes, void* hip_stream) {
+// polymul_modp's checks and launches; create_plans = false: a missing plan is an
+// error instead of being created (no device allocation).
+int polymul_modp_run(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
+                     size_t ws_bytes, hipStream_t stream, bool create_plans, const char* where) {
   try {
-    hipStream_t stream = (hipStream_t)hip_stream;
     if (la == 0 || lb == 0) return ok();
     if (!a || !b || !c) return fail(NTT_EINVAL, "NULL operand pointer");
     ProductShape s;
@@ -1062,7 +1056,7 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     if (ws_bytes < need || (need && !workspace))
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
     ntt_plan* pl = nullptr;
-    rc = cached_plan(p, (uint32_t)s.L, &pl);
+    rc = cached_plan(p, (uint32_t)s.L, &pl, false, true, create_plans);
     if (rc) return rc;
     if (s.split) {
       SplitArgs x;
@@ -1096,8 +1090,25 @@ int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb,
     rc = run_multipass_product(pl, a, la, b, lb, c, s.lc, false, workspace, stream);
     return rc ? rc : ok();
   } catch (...) {
-    return fail(NTT_EDEVICE, "exception in polymul_modp");
+    return fail(NTT_EDEVICE, "exception in %s", where);
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t polymul_workspace_bytes(uint64_t p, size_t la, size_t lb) {
+  if (la == 0 || lb == 0) return 0;
+  ProductShape s;
+  if (shape_of(p, la, lb, &s)) return 0;
+  single_path(&s);
+  return single_product_ws(s, current_cus());
+}
+
+int polymul_modp(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* workspace,
+                 size_t ws_bytes, void* hip_stream) {
+  return polymul_modp_run(p, a, la, b, lb, c, workspace, ws_bytes, (hipStream_t)hip_stream, true, "polymul_modp");
 }
 
 size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count) {
@@ -2226,6 +2237,64 @@ int ntt_arith_apply(int op, int word, uint64_t p, const void* x, const void* y, 
     return ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in ntt_arith_apply");
+  }
+}
+
+}  // extern "C"
+
+// ============================================================================ products without allocation
+// polymul_modp for callers that cannot allocate device memory: its scratch (the park
+// slice of the fused kernel, the partials of the split path, the two transformed
+// operands of the two-pass path) lives in one fixed device array of this file.  Every
+// device the library runs on holds its own copy of the array, at its own address, for
+// the life of the process.  In host code the array's name is not a device address:
+// the address is looked up once per device with hipGetSymbolAddress and only that
+// address is handed to the kernels.
+namespace {
+constexpr size_t kStaticScratchBytes = NTT_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(NTT_EDEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(NTT_EUNSUPPORTED, "device %d beyond the %d devices supported", dev,
+                                                         kMaxScratchDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(NTT_EDEVICE, "hipGetSymbolAddress of the static scratch on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return NTT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int polymul_modp_noalloc(uint64_t p, const void* a, size_t la, const void* b, size_t lb, void* c, void* hip_stream) {
+  try {
+    if (la == 0 || lb == 0) return ok();
+    ProductShape s;
+    int rc = shape_of(p, la, lb, &s);
+    if (rc) return rc;
+    single_path(&s);
+    const size_t need = single_product_ws(s, current_cus());
+    if (need > kStaticScratchBytes)
+      return fail(NTT_ENOMEM, "a product of transform length 2^%d needs %zu bytes of scratch, more than the %zu of "
+                  "polymul_modp_noalloc", s.L, need, kStaticScratchBytes);
+    void* ws = nullptr;
+    rc = scratch_address(&ws);
+    if (rc) return rc;
+    return polymul_modp_run(p, a, la, b, lb, c, ws, kStaticScratchBytes, (hipStream_t)hip_stream, false,
+                            "polymul_modp_noalloc");
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in polymul_modp_noalloc");
   }
 }
 

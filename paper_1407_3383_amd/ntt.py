@@ -50,6 +50,7 @@ EXPORTS = (
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
+    "polymul_modp_noalloc",
 )
 
 
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
         "ntt_inverse": (ci, [vp, vp, vp, sz, sz, vp, sz, vp]),
         "polymul_workspace_bytes": (sz, [u64, sz, sz]),
         "polymul_modp": (ci, [u64, vp, sz, vp, sz, vp, vp, sz, vp]),
+        "polymul_modp_noalloc": (ci, [u64, vp, sz, vp, sz, vp, vp]),
         "polymul_batch_workspace_bytes": (sz, [ctypes.POINTER(PolymulDesc), sz]),
         "polymul_modp_batch": (ci, [ctypes.POINTER(PolymulDesc), sz, vp, sz, vp]),
         "polymul_batch_create": (ci, [ctypes.POINTER(vp), ctypes.POINTER(PolymulDesc), sz]),
@@ -259,6 +261,15 @@ def polymul(a, b, p: int, out=None, stream=None, workspace=None):
     ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(need, a.device)
     _check(L.polymul_modp(p, _ptr(a), la, _ptr(b), lb, _ptr(out), _ptr(ws), ws.numel() if ws is not None else 0,
                           _stream(stream)), "polymul_modp")
+    return out
+
+
+def polymul_noalloc(a, b, p: int, out, stream=None):
+    """polymul_modp_noalloc: c = a * b mod p into the caller's `out` (la + lb - 1
+    coefficients), scratch in the library's fixed device array; the plan of (p, N)
+    must already exist (an earlier polymul call with the same p and length)."""
+    _check(load().polymul_modp_noalloc(p, _ptr(a), a.numel(), _ptr(b), b.numel(), _ptr(out), _stream(stream)),
+           "polymul_modp_noalloc")
     return out
 
 

@@ -98,6 +98,18 @@ def test_polymul_argument_errors(lib):
     assert lib.polymul_modp(998244353, one, 1 << 17, one, 1 << 17, one, None, 0, None) == ntt.NTT_ENOMEM
 
 
+def test_polymul_noalloc_argument_errors(lib):
+    one = ctypes.c_void_p(16)
+    assert lib.polymul_modp_noalloc(998244353, None, 0, None, 0, None, None) == ntt.NTT_OK  # empty
+    assert lib.polymul_modp_noalloc(998244351, one, 4, one, 4, one, None) == ntt.NTT_ENOTPRIME
+    assert lib.polymul_modp_noalloc(998244353, one, 1 << 22, one, (1 << 22) + 2, one, None) == ntt.NTT_ENOROOT
+    # two-pass scratch 2 N words: 2^23 32-bit words (N = 2^22) fit the fixed array, N = 2^23 does not
+    assert lib.polymul_modp_noalloc(998244353, one, 1 << 22, one, (1 << 22) + 1, one, None) == ntt.NTT_ENOMEM
+    assert b"more than the 33554432" in lib.ntt_last_error()
+    p62 = nt.largest_prime_below(62, 32)
+    assert lib.polymul_modp_noalloc(p62, one, 1 << 21, one, 2, one, None) == ntt.NTT_ENOMEM
+
+
 def test_intmul_argument_errors(lib):
     vp = ctypes.c_void_p
     one = vp(16)
