@@ -28,15 +28,17 @@ if ROOT not in sys.path:
 METRIC = "NTT polymul mod p: Gbutterflies/s, % HBM roofline, batched vs per-call"
 P = 2013265921
 HBM_PEAK_GBPS = 8000.0
-# Integer-VALU peak: 256 CUs x 64 lanes x 2.4 GHz of 32-bit lane operations (the
-# 32-bit multiplies issue at the same rate as adds and mins on gfx950).
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic integer operations of one radix-2 butterfly with a precomputed-
-# multiplicand twiddle: 3 (Function 8 without the final correction: one high product
-# and two multiply-adds) and 5 add/sub/min for the lazy sum and difference.  The
-# 31-bit prime of this workload needs 2 more (its sums are formed from reduced
-# operands), so frac <= 0.8 even at full issue.
-OPS_PER_BFLY = 8
+# Integer-VALU ceiling of the butterflies, from the chip's unit counts and clock:
+# 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue one lane-operation per lane and clock
+# for 32-bit multiplies, multiply-adds and min (39.3 T/s) and two for plain 32-bit
+# add and subtract (78.6 T/s), as measured by paper_1407_3383_amd.valu_rates.  The
+# butterfly of this workload's 31-bit prime (every sum formed from reduced operands,
+# since 2p < 2^32 < 4p) issues a high product, two multiply-adds and two mins (5 full-
+# rate slots) plus five adds and subtracts (2.5 slots): at most 256 * 64 * 2.4e9 / 7.5
+# = 5.24 T butterflies/s.  The same butterflies on registers alone measure 4.1 T/s.
+ALU_SLOTS_PER_BFLY = 7.5
+BFLY_PEAK_G = 256 * 64 * 2.4e9 / ALU_SLOTS_PER_BFLY / 1e9
+BFLY_REGISTERS_G = 4129.0  # CT butterfly of this prime on registers alone (profiles/valu_rates.md)
 # HBM bytes per launch of the fused kernel at the default workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy's readings; valid only
 # while the kernel's sources are the ones that were measured.
@@ -234,17 +236,20 @@ def main() -> int:
             "frac": round(alg_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         },
     }
-    achieved_tops = bfly_per_step * OPS_PER_BFLY / (kern_ms * 1e-3) / 1e12
+    achieved_g = bfly_per_step / (kern_ms * 1e-3) / 1e9
     traffic, why = measured_traffic() if (items, args.log2len) == (1024, 15) else (None, "not the profiled workload")
     out["roofline"] = {
         "bound": "alu",
         "kernel": "polymul_fused_kernel<u32, 1024 threads, 2^14-word sub-problems>",
-        "achieved": round(achieved_tops, 3),
-        "peak": round(ALU_PEAK_TOPS, 3),
-        "unit": "Tops/s (32-bit integer lane operations, %d per butterfly)" % OPS_PER_BFLY,
-        "frac": round(achieved_tops / ALU_PEAK_TOPS, 4),
+        "achieved": round(achieved_g, 1),
+        "peak": round(BFLY_PEAK_G, 1),
+        "unit": "Gbfly/s (kernel time; peak = 256 CUs x 64 lanes x 2.4 GHz / %.1f issue slots per butterfly of "
+                "this prime)" % ALU_SLOTS_PER_BFLY,
+        "frac": round(achieved_g / BFLY_PEAK_G, 4),
         "traffic": traffic,
         "kernel_ms": round(kern_ms, 4),
+        "registers_only_bfly": BFLY_REGISTERS_G,
+        "frac_of_registers_only": round(achieved_g / BFLY_REGISTERS_G, 4),
     }
     if traffic is None:
         out["roofline"]["traffic_note"] = why

@@ -8,8 +8,13 @@ from __future__ import annotations
 import sys
 import time
 
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-OPS_PER_BFLY = 8
+# Integer-VALU issue: 256 CUs x 64 lanes x 2.4 GHz full-rate lane-operation slots per
+# second (32-bit multiplies, multiply-adds and min take one slot, plain add and subtract
+# half of one: measured, paper_1407_3383_amd.valu_rates).  A butterfly of a prime below
+# 2^30 (lazy ranges) takes 6 slots, one of a 31-bit prime 7.5; a multiply-add of the
+# matrix products one.
+ALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+SLOTS_PER_BFLY = 6.0
 HBM_PEAK_GBPS = 8000.0
 
 
@@ -39,11 +44,13 @@ def _time(fn, stream, steps, warmup):
     return wall_ms, e0.elapsed_time(e1) / steps
 
 
-def _alu(ops, ms):
-    """Integer-VALU roofline of a step that needs `ops` lane operations."""
-    achieved = ops / (ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
-            "unit": "Tops/s (32-bit integer lane operations)", "frac": round(achieved / ALU_PEAK_TOPS, 4)}
+def _alu(slots, ms):
+    """Integer-VALU roofline of a step that needs `slots` full-rate issue slots."""
+    achieved = slots / (ms * 1e-3) / 1e12
+    peak = ALU_SLOTS_PER_S / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "T issue slots/s (full-rate 32-bit VALU lane-operations; %.1f per butterfly)" % SLOTS_PER_BFLY,
+            "frac": round(achieved / peak, 4)}
 
 
 def _hbm(nbytes, ms):
@@ -118,7 +125,7 @@ def run(name, args):
                       "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 1),
                               "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                               "pass_bytes_per_step": 8 * n * 4},
-                      "alu": _alu(bfly * OPS_PER_BFLY, ms)})
+                      "alu": _alu(bfly * SLOTS_PER_BFLY, ms)})
     if name == "intmul":
         a, b = inputs.intmul_inputs()
         da, db = ntt.to_device(a), ntt.to_device(b)
@@ -140,7 +147,7 @@ def run(name, args):
                      {"workload": "product of two 2^21-limb (16-bit) integers, primes 998244353, 469762049, 167772161, transform length 2^22"},
                      {"ms_per_product": round(ms, 4),
                       "hbm": {"algorithmic_bytes_per_step": alg, "achieved_GBps": round(alg / (ms * 1e-3) / 1e9, 2)},
-                      "alu": _alu(bfly * OPS_PER_BFLY, ms)})
+                      "alu": _alu(bfly * SLOTS_PER_BFLY, ms)})
     if name == "intmul32":
         # the same two integers as the integer-product configuration, in 32-bit chunks
         # (section 5.3's choice of h for these primes): transform length 2^21
@@ -165,7 +172,7 @@ def run(name, args):
                      {"workload": "product of the same two 2^25-bit integers as 2^20 chunks of 32 bits (h = 32 by "
                                   "the chunk-size rule), primes 998244353, 469762049, 167772161, transform length 2^21"},
                      {"ms_per_product": round(ms, 4), "chunk_bits": ntt.intmul_chunk_bits(a.size, b.size),
-                      "alu": _alu(bfly * OPS_PER_BFLY, ms),
+                      "alu": _alu(bfly * SLOTS_PER_BFLY, ms),
                       "hbm": _hbm(2 * a32.size * 4 + (a32.size + b32.size) * 4, ms)})
     if name == "tft":
         # TFT truncation at sub-problem granularity: 1024 products mod 2013265921 of
@@ -235,7 +242,7 @@ def run_polymatrix(args):
         macs = n ** 3 * N
         alg = (2 * n * n * d + n * n * (2 * d - 1)) * 4
         rows[n] = {"ms": round(kms, 4), "Gbfly_per_s": round(bfly / (kms * 1e-3) / 1e9, 1),
-                   "alu": _alu(bfly * OPS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
+                   "alu": _alu(bfly * SLOTS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
                    "Gmac_per_s": round(macs / (kms * 1e-3) / 1e9, 1),
                    "algorithmic_GBps": round(alg / (kms * 1e-3) / 1e9, 1),
                    "paper_cpu_s": PAPER_POLYMATRIX_S.get(n)}
@@ -428,7 +435,7 @@ def run_intmatrix(args):
         bfly = 3 * 3 * n * n * (N // 2) * 16
         macs = 3 * n ** 3 * N
         alg = (2 * n * n * na + n * n * (2 * na + 1)) * 4
-        rows[n] = {"ms": round(kms, 4), "alu": _alu(bfly * OPS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
+        rows[n] = {"ms": round(kms, 4), "alu": _alu(bfly * SLOTS_PER_BFLY + macs, kms), "hbm": _hbm(alg, kms),
                    "paper_cpu_s": PAPER_INTMATRIX_S.get(n)}
         _log("intmatrix n=%d: %.4f ms" % (n, kms))
         del dA, dB, dC, ws

@@ -16,6 +16,9 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libntt_mi355x.so")
 SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip",
            "kernels_matrix.hip", "kernels_arith.hip"]
+# Issue-rate probes of the vector ALU (measurement only, a library of their own).
+PROBE_SRC = "valu_rates.hip"
+PROBE_LIB = os.path.join(HERE, "libvalu_rates.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -45,7 +48,18 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-shared", "-o", tmp, os.path.join(CSRC, PROBE_SRC)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
