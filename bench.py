@@ -43,7 +43,7 @@ BFLY_REGISTERS_G = 4129.0  # CT butterfly of this prime on registers alone (prof
 # FETCH_SIZE / WRITE_SIZE counter runs scaled by a plain copy's readings; valid only
 # while the kernel's sources are the ones that were measured.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "polymul_fused_kernel_batch1024_n65536.md")
-KERNEL_SOURCES = ["arith.hpp", "common.hpp", "kernels.hpp", "ntt_lds.hpp", "ntt_wave.hpp", "kernels_poly.hip"]
+KERNEL_SOURCES = ["arith.hpp", "common.hpp", "kernels.hpp", "ntt_lds.hpp", "ntt_wave.hpp", "polymul_fused.hpp", "kernels_poly_w32c3.hip"]
 
 
 def log(msg: str):
