@@ -292,11 +292,28 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   };
 
   // Fold inputs: the same positions of a and b for every sub-problem.  They are
-  // requested for sub-problem h + 1 at the end of the wave phase of h, when the wave
-  // phase's registers are free, so that the loads are in flight across the barrier.
+  // requested at the start of the boundary phase of h and are in flight while G' of
+  // h - 1 computes and parks.  Requested earlier (during the wave phase) they would
+  // be live across it and spill.  When both operands cover [0, 2S) the loads carry no
+  // predicates: they issue as one burst, without a branch per load.
   T x0[EPT], x1[EPT], y0[EPT], y1[EPT];
+  const bool full2 = nsub > 1 && la >= (uint64_t)2 * S && lb >= (uint64_t)2 * S;
   auto request_fold_inputs = [&]() {
     const int tq = opaque_tid();
+    if (full2) {
+#pragma unroll
+      for (int i = 0; i < CPT; ++i)
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const int e = i * C + cc;
+          const uint32_t j = (uint32_t)(tq + i * NT) + 1024u * cc;
+          x0[e] = a[j];
+          y0[e] = b[j];
+          x1[e] = a[j + S];
+          y1[e] = b[j + S];
+        }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < CPT; ++i)
 #pragma unroll
@@ -309,9 +326,9 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         y1[e] = (nsub > 1 && j + S < lb) ? b[j + S] : (T)0;
       }
   };
-  request_fold_inputs();
   for (int h = 0; h < lam; ++h) {
     const int t0 = opaque_tid();
+    request_fold_inputs();
     // ---- boundary phase: G' of h-1 and park, fold + G of h
     if constexpr (MAXD > 0) {
       if (h > 0) finish(h - 1, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
@@ -379,7 +396,6 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
       }
       inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
     }
-    if (h + 1 < lam) request_fold_inputs();
     __syncthreads();
   }
   // ---- last boundary: G' of the last sub-problem and the recombination
@@ -436,10 +452,18 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
           gs_bfly<LAZY, true>(ar, u2, u3, w3);
           gs_bfly<LAZY, true>(ar, u0, u2, w1);
           gs_bfly<LAZY, true>(ar, u1, u3, w1);
-          if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
-          if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
-          if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u2);
-          if (jj + 3 * (uint64_t)S < lc) c[jj + 3 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u3);
+          if (lc >= (uint64_t)4 * S - 1) {  // every output but possibly the very last one exists
+            const uint32_t j32 = (uint32_t)j;
+            c[j32] = canon_from_inv<LAZY>(ar, u0);
+            c[j32 + S] = canon_from_inv<LAZY>(ar, u1);
+            c[j32 + 2 * S] = canon_from_inv<LAZY>(ar, u2);
+            if (j32 + 3 * S < (uint32_t)lc) c[j32 + 3 * S] = canon_from_inv<LAZY>(ar, u3);
+          } else {
+            if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, u0);
+            if (jj + S < lc) c[jj + S] = canon_from_inv<LAZY>(ar, u1);
+            if (jj + 2 * (uint64_t)S < lc) c[jj + 2 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u2);
+            if (jj + 3 * (uint64_t)S < lc) c[jj + 3 * (uint64_t)S] = canon_from_inv<LAZY>(ar, u3);
+          }
         }
       }
     });
