@@ -129,6 +129,37 @@ int ntt_forward(const ntt_plan* plan, const void* in, void* out, size_t batch, s
 int ntt_inverse(const ntt_plan* plan, const void* in, void* out, size_t batch, size_t stride_elems,
                 void* workspace, size_t ws_bytes, void* hip_stream);
 
+/* ---------------------------------------------------------------- truncated transforms
+ * Section 5.1: the truncated Fourier transform of an l-tuple (a_0, ..., a_(l-1)) is
+ *     TFT(a) = (A(w^[0]_k), ..., A(w^[l-1]_k)),  A(X) = a_0 + a_1 X + ... + a_(l-1) X^(l-1),
+ * the first l values of the transform in the TFT (bit-reversed) order, n = 2^k the
+ * plan's length.  Algorithm 1 computes it with n1 = 2^row_log2 (ntt_plan_get_info):
+ * only the first ceil(l / n1) rows of its step 3 run; one-pass plans transform whole
+ * vectors in LDS.  The inverse recovers the l coefficients from the l values by the
+ * inverse TFT (invert steps 4 to 1 of Algorithm 1 with the inverse TFT on the columns,
+ * and on the one row that a general l leaves partially known).
+ * Supported: plans of 32- or 64-bit words whose columns are at most 2^10 words (n <=
+ * 2^24 for the default row lengths); others return NTT_EUNSUPPORTED.  The plan's flags
+ * (bit orders) do not apply: input coefficients are in natural order, values in TFT order. */
+
+/* Device scratch of ntt_tft_forward / ntt_tft_inverse for `batch` vectors (0 for
+ * one-pass plans). */
+size_t ntt_tft_workspace_bytes(const ntt_plan* plan, size_t batch);
+
+/* out[b * out_stride + i] = A_b(w^[i]_k) for i < l_out, where A_b has the l_in
+ * coefficients in[b * in_stride + j], j < l_in (zero above), for b < batch.
+ * 0 <= l_in, l_out <= n, l_in <= in_stride, l_out <= out_stride.
+ * Errors: NTT_EINVAL (NULL/misaligned pointers, lengths), NTT_ENOMEM (workspace),
+ * NTT_EUNSUPPORTED (plan shape, residues in doubles), NTT_EDEVICE. */
+int ntt_tft_forward(const ntt_plan* plan, const void* in, size_t l_in, void* out, size_t l_out, size_t batch,
+                    size_t in_stride, size_t out_stride, void* workspace, size_t ws_bytes, void* hip_stream);
+
+/* The inverse: out[b * out_stride + j], j < l, receives the unique coefficients whose
+ * first l TFT values are in[b * in_stride + i], i < l (canonical residues).  0 <= l <= n.
+ * Errors as ntt_tft_forward. */
+int ntt_tft_inverse(const ntt_plan* plan, const void* in, void* out, size_t l, size_t batch, size_t in_stride,
+                    size_t out_stride, void* workspace, size_t ws_bytes, void* hip_stream);
+
 /* ---------------------------------------------------------------- polynomial products
  * Section 5.2: the product of two polynomials over F_p by two forward transforms,
  * an entry-wise product and one inverse transform, after zero padding to the

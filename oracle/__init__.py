@@ -151,6 +151,16 @@ def tft_order(a_hat: np.ndarray) -> np.ndarray:
     return a_hat[bitrev_perm(k)]
 
 
+def tft(a, n: int, l_out: int, p: int, w: int) -> np.ndarray:
+    """TFT_w of section 5.1 for a transform length n: the input (len(a) <= n
+    coefficients, zero beyond) transformed by the textbook transform, reordered into
+    the TFT order, and its first l_out values kept."""
+    x = np.zeros(n, dtype=np.uint64)
+    v = _u64(a)
+    x[:v.size] = v
+    return tft_order(ntt(x, p, w))[:l_out].copy()
+
+
 def horner(a, p: int, x: int) -> int:
     """A(x) = sum_j a_j x^j (section 5.1: a_hat_i = A(w^i))."""
     v = _u64(a)

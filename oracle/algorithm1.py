@@ -76,3 +76,23 @@ def algorithm1(a, l: int, n: int, n1: int, w: int, p: int) -> list[int]:
     chat = _tft_vectors(c, n1, k1, pow(w, n2, p), p)
     # Step 4: (c^_{[0],0}, ..., c^_{[n1-1],0}, c^_{[0],1}, ..., c^_{[n1-1],lambda-1}).
     return [chat[j1][j2] for j2 in range(lam) for j1 in range(n1)]
+
+
+def itft_definition(values, l: int, n: int, w: int, p: int) -> list[int]:
+    """The inverse truncated transform by definition: the unique l-tuple
+    (a_0, ..., a_{l-1}) whose TFT_w of section 5.1 is `values`, i.e. the solution of
+    sum_j a_j x_i^j = values_i, x_i = w^[i]_k (i < l), a Vandermonde system over F_p
+    with distinct points, solved by Gauss-Jordan elimination.  O(l^3): small l only."""
+    k = n.bit_length() - 1
+    xs = [pow(w, mirror(i, k), p) for i in range(l)]
+    m = [[pow(x, j, p) for j in range(l)] + [int(values[i]) % p] for i, x in enumerate(xs)]
+    for col in range(l):
+        piv = next(r for r in range(col, l) if m[r][col] % p)
+        m[col], m[piv] = m[piv], m[col]
+        inv = pow(m[col][col], p - 2, p)
+        m[col] = [v * inv % p for v in m[col]]
+        for r in range(l):
+            if r != col and m[r][col]:
+                f = m[r][col]
+                m[r] = [(vr - f * vc) % p for vr, vc in zip(m[r], m[col])]
+    return [m[i][l] for i in range(l)]

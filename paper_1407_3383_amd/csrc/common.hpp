@@ -55,6 +55,12 @@ struct PassConst {
   TwPair<T> one;      // (1, floor(2^bits(T) / p)): Function 8 by 1 reduces any word to [0, 2p)
   uint32_t L, L1, L2, B;
   double rcp32;       // 2^32 / p rounded: estimates Shoup companions of 32-bit residues
+  // Truncated transforms (section 5.1's TFT at row granularity):
+  TwPair<T> sigma_row;    // 2^bits(T) / 2^L2 mod p: the Montgomery scale of a product
+                          // whose row inverse is normalized and whose columns are
+                          // inverted exactly (inverse TFT)
+  T half;                 // (p + 1) / 2 = 2^-1 mod p
+  TwPair<T> inv2pow[16];  // 2^-m mod p, m < 16: normalization of inverse sub-blocks
 };
 
 }  // namespace nttgpu

@@ -305,7 +305,7 @@ struct ntt_plan {
   bool numeric;  // residues held in doubles (FP64 arithmetic), p < 2^49
   void* dmem;
   size_t dbytes;
-  const void *tw, *twi, *tlo, *thi, *tilo, *tihi, *tihin, *polyc, *passc;
+  const void *tw, *twi, *tlo, *thi, *tilo, *tihi, *tihin, *tihin1, *polyc, *passc;
 };
 
 namespace {
@@ -438,21 +438,38 @@ int build_plan_tables(ntt_plan* pl) {
   sc.L2 = pl->L2;
   sc.B = pl->B;
   sc.rcp32 = 4294967296.0 / (double)p;
+  {
+    // truncated transforms: the row inverse is normalized by 2^-L2 (the product's
+    // Montgomery scale 2^W / 2^L2, 1 / 2^L2 for doubles) and sub-blocks by 2^-m
+    const uint64_t inv2 = (p + 1) / 2;
+    uint64_t pw = 1;
+    for (int m = 0; m < 16; ++m) {
+      sc.inv2pow[m] = pair_of<T>(pw, p);
+      pw = mulmod(pw, inv2, p);
+    }
+    const uint64_t inv_n1 = powmod(inv2, pl->passes > 1 ? pl->L2 : (uint32_t)L, p);
+    const uint64_t rw = kNumeric ? 1 : (uint64_t)((((u128)1) << W) % p);
+    sc.sigma_row = pair_of<T>(mulmod(rw, inv_n1, p), p);
+    sc.half = (T)inv2;
+  }
   const size_t o_sc = blob.add(&sc, sizeof(sc));
-  size_t o_lo = 0, o_hi = 0, o_ilo = 0, o_ihi = 0, o_ihin = 0;
+  size_t o_lo = 0, o_hi = 0, o_ilo = 0, o_ihi = 0, o_ihin = 0, o_ihin1 = 0;
   if (pl->passes > 1) {
     const int B = (int)pl->B;
-    std::vector<TwPair<T>> lo, hi, ilo, ihi, ihin;
+    std::vector<TwPair<T>> lo, hi, ilo, ihi, ihin, ihin1;
     build_powers<T>(pl->w, p, (size_t)1 << B, 1, lo);
     build_powers<T>(powmod(pl->w, 1ull << B, p), p, (size_t)1 << (L - B), 1, hi);
     build_powers<T>(pl->winv, p, (size_t)1 << B, 1, ilo);
     build_powers<T>(powmod(pl->winv, 1ull << B, p), p, (size_t)1 << (L - B), 1, ihi);
     build_powers<T>(powmod(pl->winv, 1ull << B, p), p, (size_t)1 << (L - B), pl->ninv, ihin);
+    // the inverse twist with 2^-L2: normalized row inverses (inverse truncated transform)
+    build_powers<T>(powmod(pl->winv, 1ull << B, p), p, (size_t)1 << (L - B), powmod((p + 1) / 2, pl->L2, p), ihin1);
     o_lo = blob.add(lo.data(), lo.size() * sizeof(TwPair<T>));
     o_hi = blob.add(hi.data(), hi.size() * sizeof(TwPair<T>));
     o_ilo = blob.add(ilo.data(), ilo.size() * sizeof(TwPair<T>));
     o_ihi = blob.add(ihi.data(), ihi.size() * sizeof(TwPair<T>));
     o_ihin = blob.add(ihin.data(), ihin.size() * sizeof(TwPair<T>));
+    o_ihin1 = blob.add(ihin1.data(), ihin1.size() * sizeof(TwPair<T>));
   }
   (void)N;
   void* d = nullptr;
@@ -474,6 +491,7 @@ int build_plan_tables(ntt_plan* pl) {
   pl->tilo = pl->passes > 1 ? base + o_ilo : nullptr;
   pl->tihi = pl->passes > 1 ? base + o_ihi : nullptr;
   pl->tihin = pl->passes > 1 ? base + o_ihin : nullptr;
+  pl->tihin1 = pl->passes > 1 ? base + o_ihin1 : nullptr;
   return NTT_OK;
 }
 
@@ -743,6 +761,221 @@ int run_transform(const ntt_plan* pl, bool inverse, const void* in, void* out, s
 
 }  // namespace
 
+// ---------------------------------------------------------------------------- truncated transforms
+// Section 5.1's TFT.  Two-pass plans truncate at row granularity (Algorithm 1 with n1 =
+// 2^L2: only the first lambda rows of step 3 run) on the wave kernels' shapes.
+bool tft_rows_ok(const ntt_plan* pl) {
+  if (pl->passes == 1) return true;
+  if (pl->L1 > 10) return false;
+  return pl->wbits == 32 ? (pl->L2 >= 12 && pl->L2 <= 14) : (pl->L2 >= 12 && pl->L2 <= 13);
+}
+
+template <typename T>
+TftArgs tft_args(const ntt_plan* pl) {
+  TftArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pc = pl->passc;
+  a.tw = pl->tw;
+  a.twi = pl->twi;
+  a.tlo = pl->tlo;
+  a.thi = pl->thi;
+  a.tilo = pl->tilo;
+  a.tihi = pl->tihi;  // the inverse TFT is normalized: no n^-1 in the untwist
+  a.L = pl->log2n;
+  a.L1 = pl->L1;
+  a.L2 = pl->L2;
+  return a;
+}
+
+size_t tft_ws_bytes(const ntt_plan* pl, size_t batch) {
+  if (!pl || pl->passes == 1) return 0;
+  // one row-major copy of every vector (at most all 2^L1 rows) and one row buffer
+  return align256(((size_t)1 << pl->log2n) * (pl->wbits / 8) * batch) + align256(((size_t)1 << pl->L2) * (pl->wbits / 8) * batch);
+}
+
+int tft_check(const ntt_plan* pl, const void* in, void* out, size_t batch, size_t ws_bytes, void* ws, bool* done) {
+  *done = false;
+  if (!pl) return fail(NTT_EINVAL, "plan is NULL");
+  if (pl->numeric) return fail(NTT_EUNSUPPORTED, "truncated transforms take integer-word plans");
+  if (batch == 0) {
+    *done = true;
+    return NTT_OK;
+  }
+  if (!in || !out) return fail(NTT_EINVAL, "NULL vector pointer");
+  const size_t esz = pl->wbits / 8;
+  if (!aligned_to(in, esz) || !aligned_to(out, esz)) return fail(NTT_EINVAL, "vectors must be %zu-byte aligned", esz);
+  if (batch > 0xFFFFFFFFull) return fail(NTT_EINVAL, "batch too large");
+  if (!tft_rows_ok(pl))
+    return fail(NTT_EUNSUPPORTED, "truncated transforms of length 2^%u: columns of 2^%u words exceed the supported 2^10",
+                pl->log2n, pl->L1);
+  const size_t need = tft_ws_bytes(pl, batch);
+  if (ws_bytes < need || (need && !ws)) return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != pl->device) return fail(NTT_EINVAL, "plan belongs to device %d, current device is %d", pl->device, dev);
+  return NTT_OK;
+}
+
+// out[i] = a^_[i] (TFT order) for i < l_out, from l_in coefficients (zero above).
+int run_tft_forward(const ntt_plan* pl, const void* in, size_t l_in, void* out, size_t l_out, size_t batch,
+                    size_t in_stride, size_t out_stride, void* ws, size_t ws_bytes, hipStream_t stream) {
+  bool done = false;
+  int rc = tft_check(pl, in, out, batch, ws_bytes, ws, &done);
+  if (rc || done) return rc ? rc : ok();
+  const size_t n = (size_t)1 << pl->log2n;
+  if (l_in > n || l_out > n || l_in > in_stride || l_out > out_stride)
+    return fail(NTT_EINVAL, "lengths l_in = %zu, l_out = %zu must be <= n = %zu and <= their strides", l_in, l_out, n);
+  if (l_out == 0) return ok();
+  const int wb = (int)pl->wbits;
+  if (pl->passes == 1) {
+    LdsNttArgs a;
+    memset(&a, 0, sizeof(a));
+    a.in = in;
+    a.out = out;
+    a.stride = in_stride;
+    a.out_stride = out_stride;
+    a.pc = pl->passc;
+    a.tw = pl->tw;
+    a.twi = pl->twi;
+    a.L = pl->log2n;
+    a.bitrev = 1;
+    a.batch = (uint32_t)batch;
+    a.nin = (uint32_t)l_in;
+    a.nout = (uint32_t)l_out;
+    if (l_in == 0) {  // nothing to read: every value is 0
+      for (size_t v = 0; v < batch; ++v)
+        HIP_TRY(launch_fill_u32((uint32_t*)((unsigned char*)out + v * out_stride * (wb / 8)), l_out * (wb / 32), 0u, stream));
+      return ok();
+    }
+    HIP_TRY(launch_lds_ntt(wb, false, a, stream));
+    return ok();
+  }
+  const size_t n1 = (size_t)1 << pl->L2;
+  const uint32_t lam = (uint32_t)((l_out + n1 - 1) / n1);
+  PassArgs a;
+  memset(&a, 0, sizeof(a));
+  a.pc = pl->passc;
+  a.tw = pl->tw;
+  a.twi = pl->twi;
+  a.tlo = pl->tlo;
+  a.thi = pl->thi;
+  a.batch = (uint32_t)batch;
+  a.in = in;
+  a.in_stride = in_stride;
+  a.valid = l_in;
+  a.out = ws;
+  a.out_stride = (size_t)lam * n1;
+  a.rows = lam;
+  HIP_TRY(launch_col_fwd(wb, a, (int)pl->L1, (int)pl->L2, stream));
+  a.in = ws;
+  a.in_stride = (size_t)lam * n1;
+  a.out = out;
+  a.out_stride = out_stride;
+  a.valid = l_out;
+  HIP_TRY(launch_row_fwd(wb, a, (int)pl->L1, (int)pl->L2, stream));
+  return ok();
+}
+
+// out[0 .. l) = the l coefficients whose TFT values (TFT order) are in[0 .. l).
+int run_tft_inverse(const ntt_plan* pl, const void* in, void* out, size_t l, size_t batch, size_t in_stride,
+                    size_t out_stride, void* ws, size_t ws_bytes, hipStream_t stream) {
+  bool done = false;
+  int rc = tft_check(pl, in, out, batch, ws_bytes, ws, &done);
+  if (rc || done) return rc ? rc : ok();
+  const size_t n = (size_t)1 << pl->log2n;
+  if (l > n || l > in_stride || l > out_stride)
+    return fail(NTT_EINVAL, "length l = %zu must be <= n = %zu and <= the strides", l, n);
+  if (l == 0) return ok();
+  const int wb = (int)pl->wbits;
+  const size_t esz = wb / 8;
+  if (pl->passes == 1) {
+    TftArgs a = pl->wbits == 32 ? tft_args<uint32_t>(pl) : tft_args<uint64_t>(pl);
+    a.in = in;
+    a.out = out;
+    a.in_stride = in_stride;
+    a.out_stride = out_stride;
+    a.valid = l;
+    a.lam = (uint32_t)l;
+    a.batch = (uint32_t)batch;
+    HIP_TRY(launch_vec_itft(wb, a, stream));
+    return ok();
+  }
+  const size_t n1 = (size_t)1 << pl->L2;
+  const uint32_t lam = (uint32_t)((l + n1 - 1) / n1);
+  const uint32_t lp = (uint32_t)(l - (size_t)(lam - 1) * n1);  // known values of the last row: 1 .. n1
+  unsigned char* wsb = (unsigned char*)ws;
+  void* W = wsb;  // column-domain values, lam rows per vector
+  void* rowbuf = wsb + align256(n * esz * batch);
+  const size_t wstride = (size_t)lam * n1;
+  const uint32_t full_rows = lp == n1 ? lam : lam - 1;
+  // (1) inverse row transforms of the fully known rows, normalized, untwisted
+  if (full_rows > 0) {
+    PassArgs a;
+    memset(&a, 0, sizeof(a));
+    a.pc = pl->passc;
+    a.tw = pl->tw;
+    a.twi = pl->twi;
+    a.tilo = pl->tilo;
+    a.tihi = pl->tihin1;
+    a.batch = (uint32_t)batch;
+    a.in = in;
+    a.in_stride = in_stride;
+    a.out = W;
+    a.out_stride = wstride;
+    a.rows = full_rows;
+    HIP_TRY(launch_row_inv(wb, a, (int)pl->L1, (int)pl->L2, false, stream));
+  }
+  TftArgs t = pl->wbits == 32 ? tft_args<uint32_t>(pl) : tft_args<uint64_t>(pl);
+  t.batch = (uint32_t)batch;
+  t.rowbuf = rowbuf;
+  t.rowbuf_stride = n1;
+  if (lp < n1) {
+    // (2) columns c >= lp hold lam - 1 unknown inputs: their inverse TFT, and their
+    //     value at TFT position lam - 1 (twisted as the row pass twists row lam - 1)
+    if (lam > 1) {
+      t.in = W;
+      t.in_stride = wstride;
+      t.out = out;
+      t.out_stride = out_stride;
+      t.valid = l;
+      t.lam = lam - 1;
+      t.c_lo = lp;
+      t.c_hi = (uint32_t)n1;
+      t.eval_next = 1;
+      const uint64_t wcol = powmod(pl->g, (pl->p - 1) >> pl->L1, pl->p);  // w_(2^L1)
+      const uint64_t z = powmod(wcol, brev(lam - 1, (int)pl->L1), pl->p);
+      t.zeta = z;
+      t.zeta_s = pl->wbits == 32 ? (uint64_t)(((u128)z << 32) / pl->p) : (uint64_t)(((u128)z << 64) / pl->p);
+      HIP_TRY(launch_col_itft(wb, t, stream));
+    } else {
+      // one row only: the columns above lp are zero, and so is their TFT value
+      for (size_t v = 0; v < batch; ++v)
+        HIP_TRY(launch_fill_u32((uint32_t*)((unsigned char*)rowbuf + v * n1 * esz), n1 * (esz / 4), 0u, stream));
+    }
+    // (3) the last row: lp known TFT values, known twisted inputs at c >= lp
+    t.eval_next = 0;
+    t.in = in;
+    t.in_stride = in_stride;
+    t.out = W;
+    t.out_stride = wstride;
+    t.lam = lp;
+    t.lastrow = lam - 1;
+    HIP_TRY(launch_row_itft(wb, t, stream));
+  }
+  // (4) columns c < lp (all columns when the last row is full): lam known values each
+  t.eval_next = 0;
+  t.in = W;
+  t.in_stride = wstride;
+  t.out = out;
+  t.out_stride = out_stride;
+  t.valid = l;
+  t.lam = lam;
+  t.c_lo = 0;
+  t.c_hi = lp;
+  HIP_TRY(launch_col_itft(wb, t, stream));
+  return ok();
+}
+
 // ============================================================================ C ABI
 extern "C" {
 
@@ -835,6 +1068,28 @@ int ntt_inverse(const ntt_plan* plan, const void* in, void* out, size_t batch, s
   }
 }
 
+size_t ntt_tft_workspace_bytes(const ntt_plan* plan, size_t batch) { return tft_ws_bytes(plan, batch); }
+
+int ntt_tft_forward(const ntt_plan* plan, const void* in, size_t l_in, void* out, size_t l_out, size_t batch,
+                    size_t in_stride, size_t out_stride, void* workspace, size_t ws_bytes, void* hip_stream) {
+  try {
+    return run_tft_forward(plan, in, l_in, out, l_out, batch, in_stride, out_stride, workspace, ws_bytes,
+                           (hipStream_t)hip_stream);
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in ntt_tft_forward");
+  }
+}
+
+int ntt_tft_inverse(const ntt_plan* plan, const void* in, void* out, size_t l, size_t batch, size_t in_stride,
+                    size_t out_stride, void* workspace, size_t ws_bytes, void* hip_stream) {
+  try {
+    return run_tft_inverse(plan, in, out, l, batch, in_stride, out_stride, workspace, ws_bytes,
+                           (hipStream_t)hip_stream);
+  } catch (...) {
+    return fail(NTT_EDEVICE, "exception in ntt_tft_inverse");
+  }
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------------------- products
@@ -918,15 +1173,22 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   x.batch = 1;
   x.in_u16 = u16_inputs ? 1 : 0;
   const int L1 = (int)pl->L1, L2 = (int)pl->L2;
+  // Section 5.1's TFT at row granularity: only the first lam = ceil(lc / 2^L2) rows of
+  // Algorithm 1's step 3 are needed; the columns are then inverted by the inverse TFT
+  // (the product's coefficients at positions >= lc are the known zero inputs).
+  const size_t n1 = (size_t)1 << L2;
+  const uint32_t lam = (uint32_t)((lc + n1 - 1) / n1);
+  const bool trunc = lam < (1u << L1) && !pl->numeric && tft_rows_ok(pl);
   x.in = a;
   x.out = A;
   x.valid = la;
   x.scale = 0;
+  x.rows = trunc ? lam : 0;
   HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
   x.in = b;
   x.out = B;
   x.valid = lb;
-  x.scale = 1;
+  x.scale = trunc ? 3 : 1;  // the row inverse normalized by 2^-L2 when the columns take the inverse TFT
   HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
   x.in_u16 = 0;
   x.scale = 0;
@@ -934,6 +1196,21 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   x.in2 = B;
   x.out = A;
   HIP_TRY(launch_row_polymul(wb, x, L1, L2, stream));
+  if (trunc) {
+    TftArgs t = wb == 32 ? tft_args<uint32_t>(pl) : tft_args<uint64_t>(pl);
+    t.in = A;
+    t.in_stride = N;
+    t.out = c;
+    t.out_stride = N;
+    t.valid = lc;
+    t.lam = lam;
+    t.c_lo = 0;
+    t.c_hi = (uint32_t)n1;
+    t.batch = 1;
+    HIP_TRY(launch_col_itft(wb, t, stream));
+    return NTT_OK;
+  }
+  x.rows = 0;
   x.in = A;
   x.out = c;
   x.valid = lc;

@@ -35,7 +35,10 @@ struct LdsNttArgs {
   uint32_t L;
   uint32_t bitrev;  // forward: leave TFT order; inverse: input in TFT order
   uint32_t batch;
+  uint32_t nin;     // forward: input elements per vector (the rest read as 0); 0 = all
+  uint32_t nout;    // forward: output elements stored per vector; 0 = all
   uint32_t pad;
+  uint64_t out_stride;  // elements between output vectors; 0 = stride
 };
 int lds_max_log2n(int word_bits);
 hipError_t launch_lds_ntt(int word_bits, bool inverse, const LdsNttArgs& a, hipStream_t stream);
@@ -59,7 +62,9 @@ struct PassArgs {
   uint32_t scale;   // column forward pass: 1 multiply inputs by sigma (second operand of a product),
                     // 2 reduce inputs modulo p (words that may exceed p), 0 neither
   uint32_t in_u16;  // column forward pass: input is 16-bit limbs
-  uint32_t pad;
+  uint32_t rows;    // rows of each vector that are needed (truncated transforms: the first
+                    // `rows` rows of the TFT order); 0 = all 2^L1.  Column forward pass:
+                    // only these rows are stored; row passes: only these rows run.
 };
 // Up to kMaxPassJobs passes of the same shape (word, L1, L2, batch, input type) whose
 // workgroups share one launch: job = blockIdx.y (several primes, both operands).
@@ -78,6 +83,46 @@ hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool
 hipError_t launch_row_polymul(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 int pass_max_row_log2(int word_bits);
 int pass_col_tile_log2(int word_bits);
+
+// Inverse truncated transforms (section 5.1: Algorithm 1 inverted, steps 4 to 1, with
+// the inverse TFT).  Vectors of 2^L = 2^L1 rows x 2^L2 columns (two-pass plans) or one
+// LDS-resident vector (2^L <= 2^14 for 32-bit words, 2^13 for 64-bit).
+struct TftArgs {
+  const void* in;       // TFT values (row-major in the TFT order) or column-domain values
+  void* out;
+  uint64_t in_stride, out_stride;
+  uint64_t valid;       // outputs stored per vector: positions < valid
+  const void* pc;       // PassConst<T>
+  const void* tw;       // universal tables
+  const void* twi;
+  const void* tlo;      // two-level twist tables: forward, inverse (without n^-1)
+  const void* thi;
+  const void* tilo;
+  const void* tihi;
+  void* rowbuf;         // two-pass general inverse: the twisted column values of the last
+                        // row at columns >= lastn (rowbuf_stride words per vector)
+  uint64_t rowbuf_stride;
+  uint64_t zeta;        // column pass with `eval_next`: w_(2^L1)^([lam]_L1) and its companion
+  uint64_t zeta_s;
+  double zeta_d;        // the same as a double (residues held in doubles)
+  uint32_t lam;         // known TFT values (rows for columns, elements for one vector)
+  uint32_t c_lo, c_hi;  // columns processed: [c_lo, c_hi)
+  uint32_t eval_next;   // column pass: also evaluate each column's TFT at position lam and
+                        // write it, twisted by w_N^([lam]_L1 c), to rowbuf
+  uint32_t lastrow;     // row pass: the row index r (= lam - 1 of the columns)
+  uint32_t L, L1, L2;
+  uint32_t batch;
+};
+// Column inverse TFT: each column of 2^L1 words holds `lam` known values (rows < lam of
+// `in`) and zero inputs below; the first lam inputs are recovered and stored.
+hipError_t launch_col_itft(int word_bits, const TftArgs& a, hipStream_t stream);
+// One row (r = lastrow) of 2^L2 words per vector: `lam` TFT values from `in` (positions
+// r 2^L2 + c, c < lam), known twisted column values at c >= lam from rowbuf; the
+// untwisted values at c < lam are written to out (row r).
+hipError_t launch_row_itft(int word_bits, const TftArgs& a, hipStream_t stream);
+// One LDS-resident vector of 2^L words per batch item: lam TFT values, zero inputs
+// above; the lam inputs are stored.
+hipError_t launch_vec_itft(int word_bits, const TftArgs& a, hipStream_t stream);
 
 // out[i] = in[[i]_L] for `batch` vectors of 2^L elements (bit-reversal permutation).
 hipError_t launch_bitrev_permute(int word_bits, const void* in, void* out, uint64_t in_stride, uint64_t out_stride,

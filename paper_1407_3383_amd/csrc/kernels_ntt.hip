@@ -48,11 +48,13 @@ __device__ void lds_fwd_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   const int L = (int)A.L;
   const int n = 1 << L;
   const T* in = (const T*)A.in + vec * A.stride;
-  T* out = (T*)A.out + vec * A.stride;
-  for (int i = threadIdx.x; i < n; i += NT) s[lidx(i)] = in[i];
+  T* out = (T*)A.out + vec * (A.out_stride ? A.out_stride : A.stride);
+  // truncated transforms: inputs at positions >= nin read as 0, outputs >= nout not stored
+  const int nin = A.nin ? (int)A.nin : n, nout = A.nout ? (int)A.nout : n;
+  for (int i = threadIdx.x; i < n; i += NT) s[lidx(i)] = i < nin ? in[i] : (T)0;
   __syncthreads();
   fwd_lds<T, LAZY, NT, false>(ar, s, nullptr, L, 0, 0u, (const TwPair<T>*)A.tw);
-  for (int i = threadIdx.x; i < n; i += NT) {
+  for (int i = threadIdx.x; i < nout; i += NT) {
     const int src = A.bitrev ? i : (int)brev_bits((uint32_t)i, L);
     out[i] = canon_from_fwd<LAZY>(ar, s[lidx(src)]);
   }
@@ -66,7 +68,7 @@ __device__ void lds_inv_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   const int L = (int)A.L;
   const int n = 1 << L;
   const T* in = (const T*)A.in + vec * A.stride;
-  T* out = (T*)A.out + vec * A.stride;
+  T* out = (T*)A.out + vec * (A.out_stride ? A.out_stride : A.stride);
   const TwPair<T> ninv = pc->ninv;
   for (int i = threadIdx.x; i < n; i += NT) {
     T x = ar.shoup(in[i], ninv.w, ninv.ws);  // n^-1 applied on the way in

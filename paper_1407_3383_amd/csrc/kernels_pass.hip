@@ -152,7 +152,8 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
   if constexpr (!INV) {
     const gcptr<IN_T> in = gconst<IN_T>(uni(A.in)) + vec * A.in_stride;
     // scale 1: times sigma; 2: times 1 (reduction of words that may exceed p)
-    const TwPair<T> sig = uni(ldtw<T>(A.scale == 2 ? &pc->one : &pc->sigma));
+    // scale 3: times sigma_row (products whose columns are inverted by the inverse TFT)
+    const TwPair<T> sig = uni(ldtw<T>(A.scale == 2 ? &pc->one : (A.scale == 3 ? &pc->sigma_row : &pc->sigma)));
     const bool scale = A.scale != 0;
     bool vec4 = false;
     if constexpr (sizeof(T) == 4 && sizeof(IN_T) <= 4)
@@ -236,6 +237,8 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
   }
   __syncthreads();
   const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride;
+  // forward: only the first `rows` rows of the TFT order are stored (truncated transforms)
+  const uint32_t nrow = (!INV && A.rows) ? A.rows : (1u << K);
   bool vec4o = false;
   if constexpr (sizeof(T) == 4) vec4o = C >= 4 && ((uintptr_t)(T*)out % 16) == 0 && (A.out_stride % 4) == 0;
   if (vec4o) {
@@ -244,6 +247,7 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     for (int idx = tid; idx < (cnt >> 2); idx += NT) {
       const uint32_t r = (uint32_t)idx >> lc4, cc = ((uint32_t)idx & ((C >> 2) - 1)) << 2;
       const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+      if (r >= nrow) continue;
       T x[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -268,6 +272,7 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     for (int idx = tid; idx < cnt; idx += NT) {
       const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
       const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+      if (r >= nrow) continue;
       const T x = s[cc * VS + lidx(r)];
       if constexpr (INV) {
         if (gi < A.valid) out[gi] = canon_from_inv<LAZY>(ar, x);
@@ -308,8 +313,10 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
   const int B = (int)uni(pc->B);
   const int S = (int)uni(pc->L) - 10;
   const double rcp32 = pc->rcp32;
-  const uint64_t vec = rowid >> L1;
-  const uint32_t r = (uint32_t)(rowid & ((1u << L1) - 1));
+  // rows [0, A.rows) of every vector (truncated transforms), or all 2^L1
+  const uint32_t nr = A.rows ? A.rows : (1u << L1);
+  const uint64_t vec = rowid / nr;
+  const uint32_t r = (uint32_t)(rowid % nr);
   const uint32_t Rr = brev_u(r, L1);
   const uint64_t off = (uint64_t)r << M;
   const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(uni(A.tw));
@@ -370,10 +377,15 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
         T* const sv[1] = {sa};
         fwd_W<T, LAZY, 1, M>(ar, sv, 0, 0u, tw, x);
         const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride + off;
+        // positions >= valid of the vector are not stored (a TFT of valid values)
+        const uint64_t lim = A.valid == 0 ? ~0ull : (A.valid > off ? A.valid - off : 0);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) out[wbase + 4 * (lane + 64 * k) + c] = canon_from_fwd<LAZY>(ar, x[0][4 * k + c]);
+          for (int c = 0; c < 4; ++c) {
+            const uint32_t j = (uint32_t)(wbase + 4 * (lane + 64 * k) + c);
+            if (j < lim) out[j] = canon_from_fwd<LAZY>(ar, x[0][4 * k + c]);
+          }
       }
       __syncthreads();
       return;
@@ -550,7 +562,7 @@ hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipS
 
 template <typename T, int NT, int M, int KIND>
 static hipError_t launch_row_wave(const PassJobs& a, int L1, hipStream_t stream) {
-  const uint64_t nrows = (uint64_t)a.j[0].batch << L1;
+  const uint64_t nrows = (uint64_t)a.j[0].batch * (a.j[0].rows ? a.j[0].rows : (1u << L1));
   const size_t lds = (KIND == 2 ? 2 : 1) * (size_t)lds_words(1 << M) * sizeof(T);
   auto k = row_wave_kernel<T, NT, M, KIND>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);

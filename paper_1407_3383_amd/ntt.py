@@ -50,7 +50,7 @@ EXPORTS = (
     "ntt_tune_set", "ntt_tune_get", "ntt_tune_clear", "ntt_tune_load", "ntt_plan_cache_clear",
     "ntt_graph_begin", "ntt_graph_end", "ntt_graph_launch", "ntt_graph_destroy",
     "ntt_server_create", "ntt_server_submit", "ntt_server_progress", "ntt_server_stats", "ntt_server_destroy",
-    "polymul_modp_noalloc",
+    "polymul_modp_noalloc", "ntt_tft_workspace_bytes", "ntt_tft_forward", "ntt_tft_inverse",
 )
 
 
@@ -99,6 +99,9 @@ def load(path: str = LIB_PATH):
         "ntt_workspace_bytes": (sz, [vp, sz]),
         "ntt_forward": (ci, [vp, vp, vp, sz, sz, vp, sz, vp]),
         "ntt_inverse": (ci, [vp, vp, vp, sz, sz, vp, sz, vp]),
+        "ntt_tft_workspace_bytes": (sz, [vp, sz]),
+        "ntt_tft_forward": (ci, [vp, vp, sz, vp, sz, sz, sz, sz, vp, sz, vp]),
+        "ntt_tft_inverse": (ci, [vp, vp, vp, sz, sz, sz, sz, vp, sz, vp]),
         "polymul_workspace_bytes": (sz, [u64, sz, sz]),
         "polymul_modp": (ci, [u64, vp, sz, vp, sz, vp, vp, sz, vp]),
         "polymul_modp_noalloc": (ci, [u64, vp, sz, vp, sz, vp, vp]),
@@ -552,6 +555,38 @@ class Plan:
 
     def inverse(self, x, out=None, batch: int = 1, stride: Optional[int] = None, stream=None, workspace=None):
         return self._run(load().ntt_inverse, "ntt_inverse", x, out, batch, stride or self.n, stream, workspace)
+
+    def tft(self, x, l_out: int, l_in: Optional[int] = None, out=None, batch: int = 1, in_stride: Optional[int] = None,
+            out_stride: Optional[int] = None, stream=None):
+        """ntt_tft_forward: the first l_out TFT values of each of `batch` vectors of l_in
+        coefficients."""
+        torch = _torch()
+        l_in = x.numel() // batch if l_in is None else l_in
+        in_stride = in_stride or l_in or 1
+        out_stride = out_stride or l_out or 1
+        if out is None:
+            out = torch.empty(batch * out_stride, dtype=x.dtype, device=x.device)
+        L = load()
+        need = int(L.ntt_tft_workspace_bytes(self.handle, batch))
+        ws = _workspace(need, x.device)
+        _check(L.ntt_tft_forward(self.handle, _ptr(x), l_in, _ptr(out), l_out, batch, in_stride, out_stride, _ptr(ws),
+                                 need, _stream(stream)), "ntt_tft_forward")
+        return out
+
+    def itft(self, x, l: int, out=None, batch: int = 1, in_stride: Optional[int] = None,
+             out_stride: Optional[int] = None, stream=None):
+        """ntt_tft_inverse: the l coefficients of each vector from its first l TFT values."""
+        torch = _torch()
+        in_stride = in_stride or l or 1
+        out_stride = out_stride or l or 1
+        if out is None:
+            out = torch.empty(batch * out_stride, dtype=x.dtype, device=x.device)
+        L = load()
+        need = int(L.ntt_tft_workspace_bytes(self.handle, batch))
+        ws = _workspace(need, x.device)
+        _check(L.ntt_tft_inverse(self.handle, _ptr(x), _ptr(out), l, batch, in_stride, out_stride, _ptr(ws), need,
+                                 _stream(stream)), "ntt_tft_inverse")
+        return out
 
     def close(self):
         if self.handle:

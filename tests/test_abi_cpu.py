@@ -110,6 +110,14 @@ def test_polymul_noalloc_argument_errors(lib):
     assert lib.polymul_modp_noalloc(p62, one, 1 << 21, one, 2, one, None) == ntt.NTT_ENOMEM
 
 
+def test_tft_argument_errors(lib):
+    one = ctypes.c_void_p(16)
+    assert lib.ntt_tft_workspace_bytes(None, 4) == 0
+    assert lib.ntt_tft_forward(None, one, 4, one, 4, 1, 4, 4, None, 0, None) == ntt.NTT_EINVAL
+    assert lib.ntt_tft_inverse(None, one, one, 4, 1, 4, 4, None, 0, None) == ntt.NTT_EINVAL
+    assert b"plan is NULL" in lib.ntt_last_error()
+
+
 def test_intmul_argument_errors(lib):
     vp = ctypes.c_void_p
     one = vp(16)

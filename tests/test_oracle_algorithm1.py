@@ -43,3 +43,38 @@ def test_mirror_definition():
         for i in range(1 << k):
             assert alg.mirror(alg.mirror(i, k), k) == i
             assert alg.mirror(i, k) == oracle.bitrev(i, k)
+
+
+@pytest.mark.parametrize("k,l", [(0, 1), (1, 1), (3, 5), (4, 1), (4, 9), (5, 17), (5, 32), (6, 40), (6, 63)])
+def test_itft_definition_inverts_the_tft(k, l):
+    # the inverse TFT by its definition (a linear solve) recovers the l-tuple from its l values
+    p, g = 998244353, 3
+    n = 1 << k
+    w = nt.root_of_unity(p, n, g)
+    r = random.Random(100 * k + l)
+    a = [r.randrange(p) for _ in range(l)]
+    v = alg.tft_definition(a, l, n, w, p)
+    assert alg.itft_definition(v, l, n, w, p) == a
+
+
+def test_itft_definition_full_length_is_the_inverse_transform():
+    # with l = n the inverse TFT is the inverse transform of the values put back in natural order
+    p, g, k = 469762049, 3, 5
+    n = 1 << k
+    w = nt.root_of_unity(p, n, g)
+    r = random.Random(7)
+    vals = [r.randrange(p) for _ in range(n)]
+    nat = np.zeros(n, dtype=np.uint64)
+    for i in range(n):
+        nat[alg.mirror(i, k)] = vals[i]
+    assert alg.itft_definition(vals, n, n, w, p) == [int(x) for x in oracle.intt(nat, p, w)]
+
+
+@pytest.mark.parametrize("k,lin,lout", [(4, 16, 16), (5, 7, 20), (6, 33, 5), (6, 1, 64)])
+def test_tft_helper_matches_definition(k, lin, lout):
+    p, g = 2013265921, 31
+    n = 1 << k
+    w = nt.root_of_unity(p, n, g)
+    r = random.Random(lin * 7 + lout)
+    a = [r.randrange(p) for _ in range(lin)]
+    assert [int(x) for x in oracle.tft(np.array(a, dtype=np.uint64), n, lout, p, w)] == alg.tft_definition(a, lout, n, w, p)
