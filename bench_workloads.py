@@ -190,11 +190,35 @@ def run(name, args):
             del bt, dA, dB, dC
         full = 1024 * 3 * (1 << 15) * 16
         _log("tft: %.4f ms truncated, %.4f ms full" % (res[20000], res[1 << 15]))
+        # Two-pass products truncated at row granularity (only ceil(lc / 2^L2) rows of the
+        # row pass, the columns inverted by the inverse TFT; tuning key tft.rows = 1) against
+        # the same products at full transform length (tft.rows = 0, the default)
+        L = ntt.load()
+        two = {}
+        p62 = ntt.find_prime(62, 32)
+        for (p, la) in ((998244353, 300000), (998244353, 600000), (2013265921, 140000), (p62, 300000)):
+            a = ntt.to_device(inputs.residues(p, la, inputs.CFG_TEST, 31, 0))
+            b = ntt.to_device(inputs.residues(p, la, inputs.CFG_TEST, 31, 1))
+            c = torch.empty(2 * la - 1, dtype=a.dtype, device="cuda")
+            ws = torch.empty(max(1, L.polymul_workspace_bytes(p, la, la)), dtype=torch.uint8, device="cuda")
+            row = {}
+            outs = {}
+            for mode in (1, 0):
+                ntt.tune_set("tft.rows.w%d" % ntt.word_bits(p), mode)
+                ms2, kms2 = _time(lambda: ntt.polymul(a, b, p, out=c, stream=stream, workspace=ws), stream, 20, 3)
+                row["truncated_ms" if mode else "full_length_ms"] = round(ms2, 4)
+                outs[mode] = c.clone()
+            ntt.tune_set("tft.rows.w%d" % ntt.word_bits(p), 0)  # the default: full length
+            N = 1 << (2 * la - 2).bit_length()
+            row.update({"p": p, "operand_len": la, "transform_len": N, "identical": bool(torch.equal(outs[0], outs[1])),
+                        "time_ratio": round(row["truncated_ms"] / row["full_length_ms"], 4)})
+            two["%d_%d" % (p, la)] = row
+            _log("tft two-pass p=%d L=%d: %.4f ms truncated, %.4f ms full" % (p, la, row["truncated_ms"], row["full_length_ms"]))
         return _line("batched polymul with TFT truncation, 1024 x (20000 x 20000) mod 2013265921 (ms per launch)",
                      res[20000], "ms", res[20000], max(args.steps, 50), 10,
                      {"workload": "1024 products of length-20000 operands, transform length 2^16, 3 of 4 sub-problems"},
                      {"higher_is_better": False, "full_length_ms": round(res[1 << 15], 4),
-                      "time_ratio": round(res[20000] / res[1 << 15], 4),
+                      "time_ratio": round(res[20000] / res[1 << 15], 4), "two_pass_single_products": two,
                       "note": "untruncated, both batches would take the same time (same transform length)"})
     if name == "polymatrix":
         return run_polymatrix(args)

@@ -239,6 +239,13 @@ int polymul_batch_destroy(ntt_batch* batch);
  *                     2^(L-d) points on 2^d workgroups at once, then recombines them
  *                     (latency path; workspace N words): d = 1, 2 or 3 with
  *                     10 <= L - d <= 13 (32-bit) / 12 (64-bit), or 0 (default: off)
+ *   "server.copy_threads"  host threads (besides the caller) that copy operands into and
+ *                     products out of a serving loop's staging: 0 .. 63 (default 7), read
+ *                     by ntt_server_create
+ *   "tft.rows.w32", "tft.rows.w64"  1: two-pass products run only the first
+ *                     ceil(lc / 2^row_log2) rows of their transforms (section 5.1's TFT)
+ *                     and invert the columns by the inverse TFT; 0 (default): full-length
+ *                     transforms
  * A choice applies to plans created afterwards: clear the plan cache to re-plan.
  * Every choice computes the same (unique, canonical) results.
  * ntt_tune_set / ntt_tune_get: NTT_EINVAL for an unknown key, a value out of range
@@ -312,7 +319,10 @@ typedef struct ntt_server ntt_server;
 int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t max_batch);
 int ntt_server_submit(ntt_server* server, uint64_t id, int kind, uint64_t p, const void* a, size_t la,
                       const void* b, size_t lb, void* c);
-/* done_ids receives at most cap ids; *ndone how many. */
+/* done_ids receives at most cap ids of completed requests, *ndone how many; completed
+ * requests beyond cap are handed back by later calls (stats count them as in flight).
+ * If a batch cannot be enqueued (NTT_EDEVICE, NTT_ENOMEM), its requests return to the
+ * front of the queue and its memory to the arena before the error is returned. */
 int ntt_server_progress(ntt_server* server, uint64_t* done_ids, size_t cap, size_t* ndone);
 int ntt_server_stats(const ntt_server* server, size_t* pending, size_t* inflight, size_t* arena_used,
                      size_t* max_inflight);

@@ -59,6 +59,9 @@ bool capturing(hipStream_t s) {
 //                     one-workgroup kernel
 //   single.split.w<W>.L<L>  split depth d of a single product of length 2^L over 2^d
 //                     workgroups (0: not split)
+//   tft.rows.w<W>     two-pass products truncated at row granularity (1) or transformed at
+//                     full length (0, the default)
+//   server.copy_threads  host copy threads of a serving loop created afterwards
 std::mutex g_tune_mu;
 std::map<std::string, int64_t> g_tune;
 
@@ -78,6 +81,8 @@ bool tune_valid(const std::string& key, int64_t v) {
     if (L < 11 || L > fused_max_log2n(w)) return false;
     return v == 0 || split_supported(w, L, (int)v);
   }
+  if (sscanf(key.c_str(), "tft.rows.w%d%c", &w, &tail) == 1) return (w == 32 || w == 64) && (v == 0 || v == 1);
+  if (key == "server.copy_threads") return v >= 0 && v <= 63;
   if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
     if (w == 32) return v >= 14 && v <= 16;
     if (w == 64) return v >= 13 && v <= 15;
@@ -1178,7 +1183,10 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   // (the product's coefficients at positions >= lc are the known zero inputs).
   const size_t n1 = (size_t)1 << L2;
   const uint32_t lam = (uint32_t)((lc + n1 - 1) / n1);
-  const bool trunc = lam < (1u << L1) && !pl->numeric && tft_rows_ok(pl);
+  // (measured on gfx950: the column inverse TFT costs more than the rows it saves, so
+  // this is a tuning choice, off by default)
+  const bool trunc = lam < (1u << L1) && !pl->numeric && tft_rows_ok(pl) &&
+                     tune_value(tune_key("tft.rows", wb, -1), 0) != 0;
   x.in = a;
   x.out = A;
   x.valid = la;

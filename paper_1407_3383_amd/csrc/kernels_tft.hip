@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "ntt_cols.hpp"
 
 namespace nttgpu {
 
@@ -59,77 +60,92 @@ __device__ __forceinline__ TftOps<T> tft_ops(const void* pcv) {
   return o;
 }
 
-// Normalized inverse of the block (d, h) transform of 2^m words at offset `off` of nv
-// vectors (vector v at s + v vs, element j at lidx(j)): Gentleman-Sande stages, then the
-// factor 2^-m.
-template <typename T, int NT>
-__device__ void inv_block_norm(const TftOps<T>& o, T* s, int vs, int nv, int off, int d, uint32_t h, int m,
-                               gcptr<TwPair<T>> twi, gcptr<PassConst<T>> pc) {
-  const int tid = threadIdx.x;
-  if (m > 0) {
-    const int np = 1 << (m - 1);
-    for (int t = m - 1; t >= 0; --t) {
-      const int lh = m - t - 1;
-      const int half = 1 << lh;
-      for (int idx = tid; idx < nv * np; idx += NT) {
-        const int v = idx >> (m - 1), q = idx & (np - 1);
-        const int b = q >> lh, j = q & (half - 1);
-        const int e0 = off + (b << (lh + 1)) + j;
-        const TwPair<T> wi = ldtw<T>(twi + ((1u << (d + t)) + (h << t) + (uint32_t)b));
-        T* sv = s + v * vs;
-        const T X = sv[lidx(e0)], Y = sv[lidx(e0 + half)];
-        sv[lidx(e0)] = o.add(X, Y);
-        sv[lidx(e0 + half)] = o.mul(o.sub(X, Y), wi);
-      }
-      __syncthreads();
-    }
-    const TwPair<T> sc = ldtw<T>(&pc->inv2pow[m]);
-    const int n = 1 << m;
-    for (int idx = tid; idx < nv * n; idx += NT) {
-      const int v = idx >> m, j = idx & (n - 1);
-      T* sv = s + v * vs;
-      sv[lidx(off + j)] = o.mul(sv[lidx(off + j)], sc);
-    }
-    __syncthreads();
+// Threads that work on a set of vectors together: a whole workgroup (barriers between
+// steps) or one wave (its own vectors; LDS operations of a wave complete in order, so
+// only the compiler needs a fence).
+template <int NTH>
+struct Group {
+  int tid;
+  __device__ __forceinline__ void sync() const {
+    if constexpr (NTH == 64) __builtin_amdgcn_wave_barrier();
+    else __syncthreads();
   }
+};
+
+// Normalized inverse of the block (d, h) transform of 2^m words at offset `off` of 2^lnv
+// vectors (vector v at s + v vs, element j at lidx(j)): Gentleman-Sande stages, then the
+// factor 2^-m.  Consecutive threads take consecutive vectors at the same position, so a
+// wave reads one twiddle.  tw / twi: the universal tables (LDS or global).
+template <typename T, int NTH>
+__device__ void inv_block_norm(const TftOps<T>& o, const Group<NTH>& g, T* s, int vs, int lnv, int off, int d,
+                               uint32_t h, int m, const TwPair<T>* twi, gcptr<PassConst<T>> pc) {
+  if (m <= 0) return;
+  const int nv = 1 << lnv;
+  const int np = 1 << (m - 1);
+  for (int t = m - 1; t >= 0; --t) {
+    const int lh = m - t - 1;
+    const int half = 1 << lh;
+    for (int idx = g.tid; idx < (np << lnv); idx += NTH) {
+      const int v = idx & (nv - 1), q = idx >> lnv;
+      const int b = q >> lh, j = q & (half - 1);
+      const int e0 = off + (b << (lh + 1)) + j;
+      const TwPair<T> wi = twi[(1u << (d + t)) + (h << t) + (uint32_t)b];
+      T* sv = s + v * vs;
+      const T X = sv[lidx(e0)], Y = sv[lidx(e0 + half)];
+      sv[lidx(e0)] = o.add(X, Y);
+      sv[lidx(e0 + half)] = o.mul(o.sub(X, Y), wi);
+    }
+    g.sync();
+  }
+  const TwPair<T> sc = ldtw<T>(&pc->inv2pow[m]);
+  for (int idx = g.tid; idx < (1 << (m + lnv)); idx += NTH) {
+    const int v = idx & (nv - 1), j = idx >> lnv;
+    T* sv = s + v * vs;
+    sv[lidx(off + j)] = o.mul(sv[lidx(off + j)], sc);
+  }
+  g.sync();
 }
 
-// Inverse TFT of nv vectors of 2^K words in LDS: on entry positions [0, lam) hold the
+// Inverse TFT of 2^lnv vectors of 2^K words in LDS: on entry positions [0, lam) hold the
 // first lam TFT values and positions [lam, 2^K) the known inputs; on exit positions
-// [0, lam) hold the inputs (positions >= lam are overwritten).  1 <= lam <= 2^K.
-template <typename T, int NT>
-__device__ void itft_vectors(const TftOps<T>& o, T* s, int vs, int nv, int K, uint32_t lam, gcptr<TwPair<T>> tw,
-                             gcptr<TwPair<T>> twi, gcptr<PassConst<T>> pc) {
-  const int tid = threadIdx.x;
+// [0, lam) hold the inputs (positions >= lam are overwritten).  1 <= lam <= 2^K.  The
+// vectors are block h0 at depth d0 of a longer transform, and their elements start at
+// element eoff of each LDS vector.
+template <typename T, int NTH>
+__device__ void itft_vectors(const TftOps<T>& o, const Group<NTH>& g, T* s, int vs, int lnv, int K, uint32_t lam,
+                             const TwPair<T>* tw, const TwPair<T>* twi, gcptr<PassConst<T>> pc, int d0 = 0,
+                             uint32_t h0 = 0, int eoff = 0) {
+  const int nv = 1 << lnv;
   const uint32_t lm = lam - 1;
   int stop = K;
-  // descent
+  // descent (the vectors are block h0 at depth d0; level i handles block h of depth d0 + i)
   for (int i = 0; i <= K; ++i) {
     const int m = K - i;
     const uint32_t mask = (1u << m) - 1;
-    const uint32_t h = m == K ? 0u : lm >> m;
-    const int off = (int)(h << m);
+    const uint32_t hl = m == K ? 0u : lm >> m;  // block index inside the vector
+    const uint32_t h = (h0 << i) | hl;
+    const int d = d0 + i;
+    const int off = eoff + (int)(hl << m);  // element offset of the level's block
     if ((lm & mask) == mask) {  // the whole block is known: one normalized inverse
-      inv_block_norm<T, NT>(o, s, vs, nv, off, i, h, m, twi, pc);
+      inv_block_norm<T, NTH>(o, g, s, vs, lnv, off, d, h, m, twi, pc);
       stop = i;
       break;
     }
     const int half = 1 << (m - 1);
     const int l = (int)(lm & mask) + 1;
-    const TwPair<T> w = ldtw<T>(tw + ((1u << i) + h));
+    const TwPair<T> w = tw[(1u << d) + h];
     if (l <= half) {
-      const int cnt = half - l;
-      for (int idx = tid; idx < nv * cnt; idx += NT) {
-        const int v = idx / cnt, j = l + idx % cnt;
+      for (int idx = g.tid; idx < ((half - l) << lnv); idx += NTH) {
+        const int v = idx & (nv - 1), j = l + (idx >> lnv);
         T* sv = s + v * vs;
         sv[lidx(off + j)] = o.add(sv[lidx(off + j)], o.mul(sv[lidx(off + j + half)], w));
       }
-      __syncthreads();
+      g.sync();
     } else {
-      inv_block_norm<T, NT>(o, s, vs, nv, off, i + 1, 2 * h, m - 1, twi, pc);
-      const int lo = l - half, cnt = half - lo;
-      for (int idx = tid; idx < nv * cnt; idx += NT) {
-        const int v = idx / cnt, j = lo + idx % cnt;
+      inv_block_norm<T, NTH>(o, g, s, vs, lnv, off, d + 1, 2 * h, m - 1, twi, pc);
+      const int lo = l - half;
+      for (int idx = g.tid; idx < ((half - lo) << lnv); idx += NTH) {
+        const int v = idx & (nv - 1), j = lo + (idx >> lnv);
         T* sv = s + v * vs;
         const T y1 = sv[lidx(off + j + half)];
         const T wy = o.mul(y1, w);
@@ -137,36 +153,37 @@ __device__ void itft_vectors(const TftOps<T>& o, T* s, int vs, int nv, int K, ui
         sv[lidx(off + j)] = y0;
         sv[lidx(off + j + half)] = o.sub(y0, wy);
       }
-      __syncthreads();
+      g.sync();
     }
   }
   // ascent
   for (int i = stop - 1; i >= 0; --i) {
     const int m = K - i;
     const uint32_t mask = (1u << m) - 1;
-    const uint32_t h = m == K ? 0u : lm >> m;
-    const int off = (int)(h << m);
+    const uint32_t hl = m == K ? 0u : lm >> m;
+    const uint32_t h = (h0 << i) | hl;
+    const int d = d0 + i;
+    const int off = eoff + (int)(hl << m);  // element offset of the level's block
     const int half = 1 << (m - 1);
     const int l = (int)(lm & mask) + 1;
     if (l <= half) {
-      const TwPair<T> w = ldtw<T>(tw + ((1u << i) + h));
-      for (int idx = tid; idx < nv * l; idx += NT) {
-        const int v = idx / l, j = idx % l;
+      const TwPair<T> w = tw[(1u << d) + h];
+      for (int idx = g.tid; idx < (l << lnv); idx += NTH) {
+        const int v = idx & (nv - 1), j = idx >> lnv;
         T* sv = s + v * vs;
         sv[lidx(off + j)] = o.sub(sv[lidx(off + j)], o.mul(sv[lidx(off + j + half)], w));
       }
     } else {
-      const TwPair<T> wi = ldtw<T>(twi + ((1u << i) + h));
-      const int cnt = l - half;
-      for (int idx = tid; idx < nv * cnt; idx += NT) {
-        const int v = idx / cnt, j = idx % cnt;
+      const TwPair<T> wi = twi[(1u << d) + h];
+      for (int idx = g.tid; idx < ((l - half) << lnv); idx += NTH) {
+        const int v = idx & (nv - 1), j = idx >> lnv;
         T* sv = s + v * vs;
         const T u = sv[lidx(off + j)], x = sv[lidx(off + j + half)];
         sv[lidx(off + j)] = o.halve(o.add(u, x));
         sv[lidx(off + j + half)] = o.halve(o.mul(o.sub(u, x), wi));
       }
     }
-    __syncthreads();
+    g.sync();
   }
 }
 
@@ -181,61 +198,130 @@ __device__ __forceinline__ T twist_e(const TftOps<T>& o, T x, uint64_t e, int B,
   return o.mul(o.mul(x, a), b);
 }
 
-// Column pass: tiles of C = 2^(TILELOG - L1) adjacent columns of one vector.
-template <typename T, int NT, int TILELOG>
-__global__ __launch_bounds__(NT) void col_itft_kernel(TftArgs A, uint64_t ntiles) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* s = (T*)smem_raw;
-  const TftOps<T> o = tft_ops<T>(A.pc);
-  const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
-  const int K = (int)A.L1, L2 = (int)A.L2;
-  const int LC = TILELOG - K < L2 ? TILELOG - K : L2;
+// Column pass: tiles of C = 2^(TILELOG - K) adjacent columns of one vector (K = L1).
+// The inputs of a column at rows >= lam are zero (a product's coefficients above its
+// length, a TFT's inputs above l).  When lam > 2^(K-1), the first half of every column's
+// TFT values is known in full: its plain inverse runs as wave-local radix-16 rounds,
+// and then y_j = u_j and v_j = u_j for j >= lam - 2^(K-1) (the partner input is zero),
+// which leaves the inverse TFT of the second half (block 1 at depth 1) with lam - 2^(K-1)
+// values, then y_j = (u_j + v_j) / 2, y_(j+half) = (u_j - v_j) / 2 (the twiddle of the
+// first stage is 1).  The universal tables' first 2^K entries are copied to LDS once;
+// each wave inverts its own columns.
+template <typename T, bool LAZY, int NT, int TILELOG, int K>
+__device__ void col_itft_body(const TftArgs& A, T* s, TwPair<T>* stw, TwPair<T>* stwi, uint64_t tile,
+                              const TftOps<T>& o, gcptr<PassConst<T>> pc) {
+  const int L2 = (int)A.L2;
+  constexpr int LC0 = TILELOG - K;
+  const int LC = LC0 < L2 ? LC0 : L2;
   const int C = 1 << LC;
-  const int VS = lds_words(1 << K) + 1;
+  constexpr int VS = lds_words(1 << K) + 1;
   const uint64_t tiles_per_vec = 1ull << (L2 - LC);
   const uint32_t lam = A.lam;
   const int B = (int)uni(pc->B);
+  constexpr int NW = NT / 64;
+  const int lcw = LC > (NW == 16 ? 4 : 3) ? LC - (NW == 16 ? 4 : 3) : 0;  // log2 columns per wave
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  Group<64> g;
+  g.tid = lane;
+  const uint64_t vec = tile / tiles_per_vec;
+  const uint32_t col0 = (uint32_t)(tile % tiles_per_vec) << LC;
+  if (col0 + (uint32_t)C <= A.c_lo || col0 >= A.c_hi) return;  // the same in every thread
+  const gcptr<T> in = gconst<T>(A.in) + vec * A.in_stride;
+  for (int idx = threadIdx.x; idx < (C << K); idx += NT) {
+    const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+    // the row passes leave values in [0, 2p) (lazy ranges): reduce on the way in
+    s[cc * VS + lidx((int)r)] = r < lam ? o.ar.red1(in[((uint64_t)r << L2) + col0 + cc]) : (T)0;
+  }
+  __syncthreads();
+  if constexpr (K >= 1) {
+    constexpr int H = 1 << (K - 1);
+    if (lam > (uint32_t)H) {
+      // plain inverse of the first half of every column (unnormalized): V half-columns per
+      // wave step, so that every wave of the tile has some
+      constexpr int CT = 1 << (LC0 > 0 ? LC0 : 0);
+      constexpr int V = CT / NW > 0 ? CT / NW : 1;
+      for (int v0 = wave * V; v0 < C; v0 += NW * V)
+        vec_inv_rounds<T, LAZY, K - 1, V, K - 1>(o.ar, s + v0 * VS, VS, lane, gconst<TwPair<T>>(A.twi));
+      __syncthreads();
+      const TwPair<T> sc = ldtw<T>(&pc->inv2pow[K - 1]);
+      const int lo = (int)lam - H;
+      if ((wave << lcw) < C) {
+        T* sw = s + (wave << lcw) * VS;
+        const int nvw = 1 << lcw;
+        for (int idx = lane; idx < (H << lcw); idx += 64) {
+          const int v = idx & (nvw - 1), j = idx >> lcw;
+          T* sv = sw + v * VS;
+          const T u = o.mul(o.ar.red1(sv[lidx(j)]), sc);  // u_j, canonical
+          sv[lidx(j)] = u;
+          if (j >= lo) sv[lidx(j + H)] = u;  // y_j = u_j and v_j = u_j: the partner input is 0
+        }
+        g.sync();
+        // the second half: block 1 at depth 1, its elements H words into each column
+        if (lo > 0) itft_vectors<T, 64>(o, g, sw, VS, lcw, K - 1, (uint32_t)lo, stw, stwi, pc, 1, 1u, H);
+        for (int idx = lane; idx < (lo << lcw); idx += 64) {
+          const int v = idx & (nvw - 1), j = idx >> lcw;
+          T* sv = sw + v * VS;
+          const T u = sv[lidx(j)], x = sv[lidx(j + H)];
+          sv[lidx(j)] = o.halve(o.add(u, x));
+          sv[lidx(j + H)] = o.halve(o.sub(u, x));
+        }
+      }
+    } else if ((wave << lcw) < C) {
+      itft_vectors<T, 64>(o, g, s + (wave << lcw) * VS, VS, lcw, K, lam, stw, stwi, pc);
+    }
+  }
+  __syncthreads();
+  const gptr<T> out = gmut<T>(A.out) + vec * A.out_stride;
+  for (int idx = threadIdx.x; idx < ((int)lam << LC); idx += NT) {
+    const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
+    const uint32_t c = col0 + cc;
+    const uint64_t gi = ((uint64_t)r << L2) + c;
+    if (c >= A.c_lo && c < A.c_hi && gi < A.valid) out[gi] = s[cc * VS + lidx((int)r)];
+  }
+  if (A.eval_next) {
+    // each column's TFT value at position lam (Horner at w_(2^K)^([lam]_K)), twisted by
+    // w_N^([lam]_K c) as the row pass twists row lam
+    TwPair<T> z;
+    z.w = (T)0;
+    z.ws = (T)0;
+    if constexpr (std::is_same<T, double>::value) z.w = A.zeta_d;
+    else {
+      z.w = (T)A.zeta;
+      z.ws = (T)A.zeta_s;
+    }
+    const uint64_t rr = brev_n(lam, K);
+    for (int cc = threadIdx.x; cc < C; cc += NT) {
+      const uint32_t c = col0 + (uint32_t)cc;
+      if (c < A.c_lo || c >= A.c_hi) continue;
+      T acc = (T)0;
+      for (int r = (int)lam - 1; r >= 0; --r) acc = o.add(o.mul(acc, z), s[cc * VS + lidx(r)]);
+      const T tv = twist_e(o, acc, rr * c, B, gconst<TwPair<T>>(A.tlo), gconst<TwPair<T>>(A.thi));
+      gmut<T>(A.rowbuf)[vec * A.rowbuf_stride + c] = tv;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NT, int TILELOG, int K>
+__global__ __launch_bounds__(NT) void col_itft_kernel(TftArgs A, uint64_t ntiles) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const TftOps<T> o = tft_ops<T>(A.pc);
+  const gcptr<PassConst<T>> pc = gconst<PassConst<T>>(uni(A.pc));
+  TwPair<T>* stw = (TwPair<T>*)smem_raw;
+  TwPair<T>* stwi = stw + (1 << K);
+  T* s = (T*)(stwi + (1 << K));
+  {
+    const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(A.tw), twi = gconst<TwPair<T>>(A.twi);
+    for (int i = threadIdx.x; i < (1 << K); i += NT) {
+      stw[i] = ldtw<T>(tw + i);
+      stwi[i] = ldtw<T>(twi + i);
+    }
+  }
+  __syncthreads();
+  const bool lazy = uni(pc->lazy) != 0;
   for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint64_t vec = tile / tiles_per_vec;
-    const uint32_t col0 = (uint32_t)(tile % tiles_per_vec) << LC;
-    if (col0 + (uint32_t)C <= A.c_lo || col0 >= A.c_hi) continue;  // the same in every thread
-    const gcptr<T> in = gconst<T>(A.in) + vec * A.in_stride;
-    for (int idx = threadIdx.x; idx < (C << K); idx += NT) {
-      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
-      // the row passes leave values in [0, 2p) (lazy ranges): reduce on the way in
-      s[cc * VS + lidx((int)r)] = r < lam ? o.ar.red1(in[((uint64_t)r << L2) + col0 + cc]) : (T)0;
-    }
-    __syncthreads();
-    itft_vectors<T, NT>(o, s, VS, C, K, lam, gconst<TwPair<T>>(A.tw), gconst<TwPair<T>>(A.twi), pc);
-    const gptr<T> out = gmut<T>(A.out) + vec * A.out_stride;
-    for (int idx = threadIdx.x; idx < ((int)lam << LC); idx += NT) {
-      const uint32_t r = (uint32_t)idx >> LC, cc = (uint32_t)idx & (C - 1);
-      const uint32_t c = col0 + cc;
-      const uint64_t gi = ((uint64_t)r << L2) + c;
-      if (c >= A.c_lo && c < A.c_hi && gi < A.valid) out[gi] = s[cc * VS + lidx((int)r)];
-    }
-    if (A.eval_next) {
-      // each column's TFT value at position lam (Horner at w_(2^L1)^([lam]_L1)), twisted
-      // by w_N^([lam]_L1 c) as the row pass twists row lam
-      TwPair<T> z;
-      z.w = (T)0;
-      z.ws = (T)0;
-      if constexpr (std::is_same<T, double>::value) z.w = A.zeta_d;
-      else {
-        z.w = (T)A.zeta;
-        z.ws = (T)A.zeta_s;
-      }
-      const uint64_t rr = brev_n(lam, K);
-      for (int cc = threadIdx.x; cc < C; cc += NT) {
-        const uint32_t c = col0 + (uint32_t)cc;
-        if (c < A.c_lo || c >= A.c_hi) continue;
-        T acc = (T)0;
-        for (int r = (int)lam - 1; r >= 0; --r) acc = o.add(o.mul(acc, z), s[cc * VS + lidx(r)]);
-        const T tv = twist_e(o, acc, rr * c, B, gconst<TwPair<T>>(A.tlo), gconst<TwPair<T>>(A.thi));
-        gmut<T>(A.rowbuf)[vec * A.rowbuf_stride + c] = tv;
-      }
-    }
-    __syncthreads();
+    if (lazy) col_itft_body<T, true, NT, TILELOG, K>(A, s, stw, stwi, tile, o, pc);
+    else col_itft_body<T, false, NT, TILELOG, K>(A, s, stw, stwi, tile, o, pc);
   }
 }
 
@@ -256,7 +342,9 @@ __global__ __launch_bounds__(NT) void row_itft_kernel(TftArgs A) {
     const gcptr<T> rb = gconst<T>(A.rowbuf) + vec * A.rowbuf_stride;
     for (int j = threadIdx.x; j < n1; j += NT) s[lidx(j)] = (uint32_t)j < lam ? in[j] : rb[j];
     __syncthreads();
-    itft_vectors<T, NT>(o, s, 0, 1, L2, lam, gconst<TwPair<T>>(A.tw), gconst<TwPair<T>>(A.twi), pc);
+    Group<NT> g;
+    g.tid = threadIdx.x;
+    itft_vectors<T, NT>(o, g, s, 0, 0, L2, lam, (const TwPair<T>*)A.tw, (const TwPair<T>*)A.twi, pc);
     const gptr<T> out = gmut<T>(A.out) + vec * A.out_stride + ((uint64_t)r << L2);
     for (int j = threadIdx.x; j < (int)lam; j += NT)
       out[j] = twist_e(o, s[lidx(j)], rr * (uint64_t)j, B, gconst<TwPair<T>>(A.tilo), gconst<TwPair<T>>(A.tihi));
@@ -278,7 +366,9 @@ __global__ __launch_bounds__(NT) void vec_itft_kernel(TftArgs A) {
     const gcptr<T> in = gconst<T>(A.in) + vec * A.in_stride;
     for (int j = threadIdx.x; j < n; j += NT) s[lidx(j)] = (uint32_t)j < lam ? in[j] : (T)0;
     __syncthreads();
-    itft_vectors<T, NT>(o, s, 0, 1, L, lam, gconst<TwPair<T>>(A.tw), gconst<TwPair<T>>(A.twi), pc);
+    Group<NT> g;
+    g.tid = threadIdx.x;
+    itft_vectors<T, NT>(o, g, s, 0, 0, L, lam, (const TwPair<T>*)A.tw, (const TwPair<T>*)A.twi, pc);
     const gptr<T> out = gmut<T>(A.out) + vec * A.out_stride;
     for (int j = threadIdx.x; j < (int)lam; j += NT)
       if ((uint64_t)j < A.valid) out[j] = s[lidx(j)];
@@ -288,18 +378,30 @@ __global__ __launch_bounds__(NT) void vec_itft_kernel(TftArgs A) {
 
 int grid_for(uint64_t items) { return (int)(items < 65536ull ? (items ? items : 1) : 65536ull); }
 
-template <typename T, int NT, int TILELOG>
-hipError_t launch_col_itft_t(const TftArgs& a, hipStream_t stream) {
-  const int K = (int)a.L1, L2 = (int)a.L2;
-  if (K > TILELOG || a.lam == 0 || a.lam > (1u << K)) return hipErrorInvalidValue;
+template <typename T, int NT, int TILELOG, int K>
+hipError_t launch_col_itft_k(const TftArgs& a, hipStream_t stream) {
+  const int L2 = (int)a.L2;
+  if (a.lam == 0 || a.lam > (1u << K)) return hipErrorInvalidValue;
   const int LC = TILELOG - K < L2 ? TILELOG - K : L2;
   const uint64_t ntiles = (uint64_t)a.batch << (L2 - LC);
-  const size_t lds = (size_t)(1 << LC) * (lds_words(1 << K) + 1) * sizeof(T);
-  auto k = col_itft_kernel<T, NT, TILELOG>;
+  const size_t lds = (size_t)(1 << LC) * (lds_words(1 << K) + 1) * sizeof(T) + 2 * ((size_t)1 << K) * sizeof(TwPair<T>);
+  auto k = col_itft_kernel<T, NT, TILELOG, K>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid_for(ntiles)), dim3(NT), lds, stream, a, ntiles);
   return hipGetLastError();
+}
+
+template <typename T, int NT, int TILELOG>
+hipError_t launch_col_itft_t(const TftArgs& a, hipStream_t stream) {
+  switch (a.L1) {
+#define NTT_ITFT_COL(KK) \
+  case KK: return launch_col_itft_k<T, NT, TILELOG, KK>(a, stream);
+    NTT_ITFT_COL(1) NTT_ITFT_COL(2) NTT_ITFT_COL(3) NTT_ITFT_COL(4) NTT_ITFT_COL(5) NTT_ITFT_COL(6) NTT_ITFT_COL(7)
+    NTT_ITFT_COL(8) NTT_ITFT_COL(9) NTT_ITFT_COL(10)
+#undef NTT_ITFT_COL
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename T, int NT, int MAXLOG>

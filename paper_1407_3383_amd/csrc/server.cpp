@@ -206,6 +206,7 @@ struct ntt_server {
   size_t max_inflight = 0;
   size_t inflight_cap = 8;  // batches in flight at once: 2 per stream, one staging block each
   CopyPool* pool = nullptr;
+  std::deque<uint64_t> finished;  // completed requests not yet handed back by progress()
 };
 
 namespace {
@@ -347,8 +348,12 @@ int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t m
   s->budget = hbm_budget;
   s->arena = new Arena(hbm_budget);
   {
+    // copy threads besides the calling one: the tuning choice server.copy_threads, else 7
+    // (bounded by the host's hardware threads)
     const unsigned hw = std::thread::hardware_concurrency();
-    s->pool = new CopyPool((int)std::min(7u, hw > 1 ? hw - 1 : 0u));  // plus the calling thread
+    int64_t want = 7;
+    if (ntt_tune_get("server.copy_threads", &want) != NTT_OK) want = 7;
+    s->pool = new CopyPool((int)std::min<int64_t>(want, hw > 1 ? hw - 1 : 0));
   }
   s->max_batch = max_batch;
   for (int i = 0; i < streams; ++i) {
@@ -413,9 +418,9 @@ int ntt_server_submit(ntt_server* s, uint64_t id, int kind, uint64_t p, const vo
 int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* ndone) {
   if (!s || !ndone || (cap && !done_ids)) return NTT_EINVAL;
   *ndone = 0;
-  // completions, in launch order per stream; a finished batch frees its memory
+  // completions, in launch order per stream; a finished batch frees its memory and its
+  // requests queue for hand-back (at most cap per call, the rest on later calls)
   for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-    if (*ndone + it->reqs.size() > cap) break;
     const hipError_t q = hipEventQuery(it->ev);
     if (q == hipErrorNotReady) {
       ++it;
@@ -427,7 +432,7 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
     for (size_t i = 0; i < it->reqs.size(); ++i) {
       const Req& r = it->reqs[i];
       if (r.c && !r.direct) cp.push_back(CopyPool::Copy{r.c, host + it->off_c[i], r.out_elems() * r.out_esz()});
-      done_ids[(*ndone)++] = r.id;
+      s->finished.push_back(r.id);
     }
     s->pool->copy(cp);
     s->staging[it->staging].busy = false;
@@ -463,9 +468,22 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
     if (!placed) break;  // wait for memory to free up
     for (size_t i = 0; i < bt.reqs.size(); ++i) s->pending.pop_front();
     int rc = launch(s, bt);
-    if (rc) return rc;
+    if (rc) {
+      // nothing of the batch is pending on the device after a failed enqueue is drained:
+      // give its memory back and return its requests to the front of the queue
+      for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+      if (bt.staging >= 0) s->staging[bt.staging].busy = false;
+      if (bt.ev) s->free_events.push_back(bt.ev);
+      s->arena->release(bt.block, bt.block_bytes);
+      for (size_t i = bt.reqs.size(); i-- > 0;) s->pending.push_front(bt.reqs[i]);
+      return rc;
+    }
     s->inflight.push_back(bt);
     s->max_inflight = std::max(s->max_inflight, s->inflight.size());
+  }
+  while (*ndone < cap && !s->finished.empty()) {
+    done_ids[(*ndone)++] = s->finished.front();
+    s->finished.pop_front();
   }
   return NTT_OK;
 }
@@ -473,7 +491,7 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
 int ntt_server_stats(const ntt_server* s, size_t* pending, size_t* inflight, size_t* arena_used, size_t* max_inflight) {
   if (!s) return NTT_EINVAL;
   if (pending) *pending = s->pending.size();
-  if (inflight) *inflight = s->inflight.size();
+  if (inflight) *inflight = s->inflight.size() + s->finished.size();
   if (arena_used) *arena_used = s->arena->used;
   if (max_inflight) *max_inflight = s->max_inflight;
   return NTT_OK;

@@ -119,9 +119,16 @@ def test_products_with_truncated_two_pass_transforms(p, la, lb):
     torch_cuda()
     a = inputs.residues(p, la, inputs.CFG_TEST, 12900 + la % 997, 0)
     b = inputs.residues(p, lb, inputs.CFG_TEST, 12900 + lb % 997, 1)
-    say("truncated product p=%d la=%d lb=%d" % (p, la, lb))
-    c = ntt.to_numpy(ntt.polymul(ntt.to_device(a), ntt.to_device(b), p))
-    assert_equal_u(c, oracle.polymul_ntt(a, b, p), "product p=%d la=%d lb=%d" % (p, la, lb))
+    want = oracle.polymul_ntt(a, b, p)
+    key = "tft.rows.w%d" % ntt.word_bits(p)
+    for mode in (1, 0):  # truncated at row granularity, then full length (the default)
+        ntt.tune_set(key, mode)
+        say("product p=%d la=%d lb=%d tft.rows=%d" % (p, la, lb, mode))
+        try:
+            c = ntt.to_numpy(ntt.polymul(ntt.to_device(a), ntt.to_device(b), p))
+        finally:
+            ntt.tune_set(key, 0)
+        assert_equal_u(c, want, "product p=%d la=%d lb=%d tft.rows=%d" % (p, la, lb, mode))
 
 
 def test_tft_argument_errors():
