@@ -137,7 +137,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="batch",
-                    choices=["batch", "polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "intmatrix", "f64", "serve", "all"],
+                    choices=["batch", "polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "intmatrix", "f64", "fft", "serve", "all"],
                     help="batch (default, the headline line) or one of the other configurations")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--matrix-n", type=int, default=0, help="polymatrix, intmatrix: one matrix size only (default 1 .. 32)")
@@ -164,7 +164,7 @@ def main() -> int:
         return 0
     if args.workload != "batch":
         import bench_workloads
-        names = (["polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "intmatrix", "f64", "serve"] if args.workload == "all"
+        names = (["polymul8k", "ntt2_24", "intmul", "intmul32", "tft", "polymatrix", "intmatrix", "f64", "fft", "serve"] if args.workload == "all"
                  else [args.workload])
         for name in names:
             print(json.dumps(bench_workloads.run(name, args)), flush=True)

@@ -224,6 +224,8 @@ def run(name, args):
         return run_polymatrix(args)
     if name == "f64":
         return run_f64(args)
+    if name == "fft":
+        return run_fft(args)
     if name == "intmatrix":
         return run_intmatrix(args)
     if name == "serve":
@@ -385,15 +387,17 @@ def run_serve(args):
 def run_f64(args):
     """Section 3's numeric-type arithmetic against the 64-bit integer words: 1024
     products of length-2^14 operands (transform length 2^15, the fused kernel's 64-bit
-    limit) modulo the largest primes below 2^48 and 2^49 with 2^20 | p - 1, and 8192
-    products of length 2^11, once with residues in doubles (Function 16) and once in
+    limit) modulo the largest primes below 2^48, 2^49 and 2^50 with 2^20 | p - 1, 8192
+    products of length 2^11, and 16 products of length-2^19 operands (two-pass
+    transforms of length 2^20), once with residues in doubles (Function 16) and once in
     64-bit integers (Function 8 over 64-bit words), same kernels otherwise."""
     import torch
 
     from paper_1407_3383_amd import inputs, ntt
     stream = torch.cuda.Stream()
     res = {}
-    for bits, items, n in ((48, 1024, 1 << 14), (49, 1024, 1 << 14), (49, 8192, 1 << 11)):
+    for bits, items, n in ((48, 1024, 1 << 14), (49, 1024, 1 << 14), (50, 1024, 1 << 14), (49, 8192, 1 << 11),
+                           (49, 16, 1 << 19), (50, 16, 1 << 19)):
         N = 2 * n
         log2N = N.bit_length() - 1
         bfly = items * 3 * (N // 2) * log2N
@@ -424,6 +428,71 @@ def run_f64(args):
                  {"workload": "1024 products of length-2^14 operands, transform length 2^15, p < 2^49 and p < 2^48"},
                  {"dtype": "f64", "by_case": res,
                   "note": "u64: the same batch with 64-bit integer residues (Function 8 over 64-bit words)"})
+
+
+# Section 5.1's tables of transform times of one core of the paper's machine (microseconds,
+# its AVX rows): length 2^8..2^20 over Z/469762049Z (32-bit words, Barrett) and over
+# Z/1108307720798209Z (doubles, FMA), for context beside the times here
+PAPER_FFT32_US = {8: 0.64, 9: 1.4, 10: 2.9, 11: 6.4, 12: 14, 13: 30, 14: 64, 15: 140, 16: 290, 17: 630, 18: 1400,
+                  19: 3000, 20: 6800}
+PAPER_FFT64_US = {8: 1.2, 9: 2.5, 10: 5.6, 11: 12, 12: 26, 13: 57, 14: 120, 15: 270, 16: 580, 17: 1200, 18: 2600,
+                  19: 6100, 20: 15000}
+
+
+def run_fft(args):
+    """Forward transforms of length 2^8..2^20 (section 5.1's two tables): mod 469762049
+    in 32-bit words, and mod 1108307720798209 = 63 * 2^44 + 1 once in 64-bit integer
+    words and once in doubles (NTT_FP64).  Per length: one transform alone (latency) and a
+    batch of 2^24 / n transforms in one call (throughput); TFT order out, as the paper's
+    FFTs leave it."""
+    import numpy as np
+    import torch
+
+    from paper_1407_3383_amd import inputs, ntt
+    stream = torch.cuda.Stream()
+    p32, p64 = 469762049, 63 * 2 ** 44 + 1
+    total = 1 << 24
+    res = {}
+    flags = ntt.NTT_BITREV_OUT
+    steps = max(args.steps, 20)
+    for log2n in range(8, 21):
+        n = 1 << log2n
+        batch = total // n
+        row = {"paper_us_32": PAPER_FFT32_US[log2n], "paper_us_fp64": PAPER_FFT64_US[log2n]}
+        ref64 = None
+        for kind, p, fl in (("u32", p32, flags), ("u64", p64, flags), ("f64", p64, flags | ntt.NTT_FP64)):
+            plan = ntt.Plan(p, log2n, 0, fl)
+            x = inputs.residues(p, total, inputs.CFG_FFT, log2n)
+            dx = torch.from_numpy(x.astype(np.float64)).cuda() if kind == "f64" else ntt.to_device(x)
+            dy = torch.empty_like(dx)
+            ws = ntt._workspace(max(plan.workspace_bytes(batch), 1), dx.device)
+            _, one_ms = _time(lambda: plan.forward(dx, out=dy, batch=1, stream=stream, workspace=ws), stream, steps, 3)
+            _, all_ms = _time(lambda: plan.forward(dx, out=dy, batch=batch, stream=stream, workspace=ws), stream,
+                              max(steps // 4, 5), 2)
+            torch.cuda.synchronize()
+            bfly = batch * (n // 2) * log2n
+            row[kind] = {"one_us": round(one_ms * 1e3, 2), "batch": batch, "batch_ms": round(all_ms, 4),
+                         "us_per_transform_in_batch": round(all_ms * 1e3 / batch, 4),
+                         "Gbfly_per_s": round(bfly / (all_ms * 1e-3) / 1e9, 1)}
+            if kind == "u64":
+                ref64 = dy.cpu().numpy()
+            elif kind == "f64":
+                row["f64_equals_u64"] = bool((dy.cpu().numpy().astype(np.uint64) == ref64.astype(np.uint64)).all())
+            plan.close()
+            del dx, dy, ws
+        res["2^%d" % log2n] = row
+        _log("fft 2^%d: u32 %.2f us / %.4f us per transform in a batch; u64 %.2f / %.4f; f64 %.2f / %.4f; f64 = u64 %s"
+             % (log2n, row["u32"]["one_us"], row["u32"]["us_per_transform_in_batch"], row["u64"]["one_us"],
+                row["u64"]["us_per_transform_in_batch"], row["f64"]["one_us"], row["f64"]["us_per_transform_in_batch"],
+                row["f64_equals_u64"]))
+    top = res["2^20"]
+    return _line("forward FFT over Z/1108307720798209Z, length 2^20, residues in doubles (Gbutterflies/s)",
+                 top["f64"]["Gbfly_per_s"], "Gbfly/s", top["f64"]["batch_ms"], max(steps // 4, 5), 2,
+                 {"workload": "forward transforms of length 2^8..2^20, 2^24 / n per call, mod 469762049 (32-bit words) "
+                              "and mod 1108307720798209 (64-bit words and doubles)"},
+                 {"dtype": "f64", "by_length": res,
+                  "note": "one_us: a single transform per call; batch: 2^24 / n transforms per call; paper_us: one "
+                          "core of the paper's machine (AVX rows), context only"})
 
 
 # Section 5.3's table of integer matrix products in bit-size 32 x 2^15 (seconds on one

@@ -46,6 +46,9 @@ enum {
 #define NTT_BITREV_OUT 1u /* forward leaves its output in bit-reversed (TFT) order     */
 #define NTT_BITREV_IN 2u  /* inverse takes its input in bit-reversed (TFT) order       */
 #define NTT_VALIDATE 4u   /* check that inputs are < p before launching (synchronous)   */
+#define NTT_FP64 8u       /* residues held in doubles (section 3, Functions 16-17): vectors of
+                             double holding the integers 0 .. p-1, p < 2^50; not with
+                             NTT_VALIDATE; transform lengths up to 2^23 */
 
 typedef struct ntt_plan ntt_plan;
 
@@ -384,7 +387,7 @@ int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, u
 
 /* Element-wise evaluation of one device primitive on n elements (a diagnostic for
  * testing the arithmetic alone; every transform kernel uses these same forms).
- * word: 32 or 64 (unsigned words, p < 2^31 or p < 2^62) or 0 (doubles, p < 2^49).
+ * word: 32 or 64 (unsigned words, p < 2^31 or p < 2^62) or 0 (doubles, p < 2^50).
  * x, y, ys, out: device arrays of the word type (ys: Shoup companions
  * floor(y 2^W / p), op NTT_ARITH_SHOUP with unsigned words only; out: n words, 2n for
  * the butterflies).  tw, tws: the butterflies' twiddle and its companion (the same in
@@ -407,16 +410,18 @@ int ntt_arith_apply(int op, int word, uint64_t p, const void* x, const void* y, 
 
 /* Products mod p with residues held in doubles (section 3: modular arithmetic over
  * numeric types; products by Function 16, the FMA product, sums by Function 17's
- * compare-and-subtract), in the same fused one-workgroup kernels as polymul_modp_batch.
+ * compare-and-subtract), in the same fused one-workgroup kernels as polymul_modp_batch
+ * for transforms up to 2^15 and in the two-pass kernels above.
  * Descriptors as for polymul_modp_batch, except that a, b and c point to device arrays
  * of double holding canonical residues (integers in [0, p)); c receives la + lb - 1
  * canonical residues as doubles.
- * p: prime below 2^49 (operands stay below 2p, or 4p for p < 2^48, between
- *   butterflies, and Function 16 needs x y < 2^50 p); transform length
- *   2^ceil(log2(la + lb - 1)) at most 2^15 and dividing p - 1.
+ * p: prime below 2^50 (Function 16 needs x y < 2^50 p: operands stay below 4p between
+ *   butterflies for p < 2^48, and multiplicands are reduced to [0, p) first above);
+ *   transform length 2^ceil(log2(la + lb - 1)) at most 2^23 and dividing p - 1.
  * workspace: polymul_f64_batch_workspace_bytes(d, count) bytes (the device copy of the
- *   descriptors).  Asynchronous on hip_stream; not recordable in a graph.
- * Errors: NTT_EUNSUPPORTED (p >= 2^49, transform longer than 2^15), NTT_ENOTPRIME,
+ *   descriptors and the two-pass products' transforms).  Asynchronous on hip_stream;
+ *   not recordable in a graph.
+ * Errors: NTT_EUNSUPPORTED (p >= 2^50, transform longer than 2^23), NTT_ENOTPRIME,
  *   NTT_ENOROOT, NTT_EINVAL (NULL or misaligned pointers, graph capture), NTT_ENOMEM
  *   (workspace too small), NTT_EDEVICE. */
 size_t polymul_f64_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace nttgpu {
 
 template <typename T>
@@ -127,14 +129,15 @@ struct Arith<uint64_t> {
 };
 
 // Residues held in doubles (section 3, numeric types: 52 explicit mantissa bits),
-// p < 2^49.  Sums of residues below 2^53 are exact, so the integer butterflies' add,
+// p < 2^50.  Sums of residues below 2^53 are exact, so the integer butterflies' add,
 // subtract and compare-and-subtract (Function 17) carry over unchanged.  The product
 // is Function 16: h = x y rounded, l = x y - h exactly (one FMA), c = floor(h u) with
 // u = 1/p rounded, d = h - c p exactly (one FMA), e = d + l = x y - c p.  For
 // x y < 2^50 p (Proposition 13 with 52 mantissa bits), c is floor(x y / p) up to one,
 // so e lies in [-p, 2p); one correction gives [0, 2p), the range the integer
 // fixed-multiplicand product leaves.  Operands stay below 4p between butterflies when
-// p < 2^48 (lazy) and below 2p otherwise, so x w < 2^50 p holds for p < 2^49.
+// p < 2^48 (lazy), so x w < 2^50 p; otherwise the butterflies reduce the multiplicand
+// to [0, p) first (mul_operand), so x w < p^2 < 2^50 p for every p < 2^50.
 // Explicit _rn operations keep the compiler from contracting h into another FMA.
 template <>
 struct Arith<double> {
@@ -157,17 +160,53 @@ struct Arith<double> {
 };
 
 // ----------------------------------------------------------------------------
-// Butterflies.  LAZY (4p < 2^bits): Harvey-style ranges; otherwise (the 31-bit
-// primes) every sum is formed from operands reduced to [0, p).
+// Arithmetic modes: the LAZY template argument of the butterflies and of every kernel
+// body above them, read from the plan's constants at run time.
+//   kLazy (4p < 2^bits; p < 2^48 for doubles): Harvey-style ranges.
+//   kSafe (the 31-bit primes; 2^48 <= p < 2^49 for doubles): every sum is formed from
+//         operands reduced to [0, p), values stay below 2p.
+//   kBand (doubles, 2^49 <= p < 2^50): as kSafe, and each multiplicand is reduced to
+//         [0, p) before its product: Function 16 needs x y < 2^50 p, which x < 2p no
+//         longer guarantees.
+constexpr int kSafe = 0;
+constexpr int kLazy = 1;
+constexpr int kBand = 2;
+
+// Calls f with the plan's arithmetic mode as a compile-time constant
+// (std::integral_constant<int, mode>); kBand is instantiated for doubles only.
+template <typename T, typename F>
+__device__ __forceinline__ void with_mode(int mode, F&& f) {
+  if (mode == kLazy) {
+    f(std::integral_constant<int, kLazy>());
+    return;
+  }
+  if constexpr (std::is_same<T, double>::value) {
+    if (mode == kBand) {
+      f(std::integral_constant<int, kBand>());
+      return;
+    }
+  }
+  f(std::integral_constant<int, kSafe>());
+}
+
+// Butterflies.
 //
 // Forward, Cooley-Tukey form (X, Y) -> (X + w Y, X - w Y):
 //   LAZY: X in [0,4p), Y < 2^bits  ->  both outputs in [0,4p)
 //   SAFE: X in [0,2p), Y < 2^bits  ->  both outputs in [0,2p)
 // UNI: the twiddle is the same in every lane (it went through uni()).
-template <bool LAZY, bool UNI = false, typename T>
+// kBand follows kSafe's ranges with the multiplicand reduced first (mul_operand).
+template <int LAZY, typename T>
+__device__ __forceinline__ T mul_operand(const Arith<T>& ar, T x) {
+  if constexpr (LAZY == kBand) return ar.red1(x);
+  else return x;
+}
+
+template <int LAZY, bool UNI = false, typename T>
 __device__ __forceinline__ void ct_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
-  T t = UNI ? ar.shoup_u(Y, tw.w, tw.ws) : ar.shoup(Y, tw.w, tw.ws);
-  if constexpr (LAZY) {
+  const T Ym = mul_operand<LAZY>(ar, Y);
+  T t = UNI ? ar.shoup_u(Ym, tw.w, tw.ws) : ar.shoup(Ym, tw.w, tw.ws);
+  if constexpr (LAZY == kLazy) {
     T x = ar.red2(X);
     X = x + t;
     Y = x - t + ar.p2;
@@ -182,30 +221,30 @@ __device__ __forceinline__ void ct_bfly(const Arith<T>& ar, T& X, T& Y, const Tw
 // Inverse, Gentleman-Sande form (X, Y) -> (X + Y, (X - Y) w):
 //   LAZY: inputs in [0,2p) -> outputs in [0,2p)
 //   SAFE: inputs in [0,p)  -> outputs in [0,p)
-template <bool LAZY, bool UNI = false, typename T>
+template <int LAZY, bool UNI = false, typename T>
 __device__ __forceinline__ void gs_bfly(const Arith<T>& ar, T& X, T& Y, const TwPair<T>& tw) {
-  if constexpr (LAZY) {
+  if constexpr (LAZY == kLazy) {
     T s = ar.red2(X + Y);
     const T d = X - Y + ar.p2;
     Y = UNI ? ar.shoup_u(d, tw.w, tw.ws) : ar.shoup(d, tw.w, tw.ws);
     X = s;
   } else {
     T s = ar.red1(X + Y);
-    const T d = X - Y + ar.p;
+    const T d = mul_operand<LAZY>(ar, X - Y + ar.p);
     Y = ar.red1(UNI ? ar.shoup_u(d, tw.w, tw.ws) : ar.shoup(d, tw.w, tw.ws));
     X = s;
   }
 }
 
 // Canonical representative from the range a butterfly left behind.
-template <bool LAZY, typename T>
+template <int LAZY, typename T>
 __device__ __forceinline__ T canon_from_fwd(const Arith<T>& ar, T x) {
-  if constexpr (LAZY) return ar.red1(ar.red2(x));
+  if constexpr (LAZY == kLazy) return ar.red1(ar.red2(x));
   else return ar.red1(x);
 }
-template <bool LAZY, typename T>
+template <int LAZY, typename T>
 __device__ __forceinline__ T canon_from_inv(const Arith<T>& ar, T x) {
-  if constexpr (LAZY) return ar.red1(x);
+  if constexpr (LAZY == kLazy) return ar.red1(x);
   else return x;
 }
 

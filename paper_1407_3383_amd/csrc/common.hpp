@@ -19,7 +19,7 @@ namespace nttgpu {
 // below (entry (r, c) multiplies u_c into u_(lambda + r)).
 template <typename T>
 struct PolyConst {
-  T p, p2, pinv, lazy;  // lazy = 1 when 4p < 2^bits(T)
+  T p, p2, pinv, lazy;  // the arithmetic mode: 1 lazy ranges, 0 values below 2p, 2 doubles, p >= 2^49
   TwPair<T> fa[4][4];   // psi_h^k
   TwPair<T> fb[4][4];   // psi_h^k * sigma, sigma = 2^bits(T) / N mod p (Montgomery scale)
   TwPair<T> tft2[3];        // d = 2, lambda = 3: 1 x 3
@@ -49,7 +49,7 @@ struct FusedItem {
 // factor an entry of the universal table (same in every lane).
 template <typename T>
 struct PassConst {
-  T p, p2, pinv, lazy;
+  T p, p2, pinv, lazy;  // the arithmetic mode, as in PolyConst
   TwPair<T> ninv;     // n^-1
   TwPair<T> sigma;    // 2^bits(T) / N mod p
   TwPair<T> one;      // (1, floor(2^bits(T) / p)): Function 8 by 1 reduces any word to [0, 2p)

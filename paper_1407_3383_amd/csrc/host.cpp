@@ -306,8 +306,8 @@ struct ntt_plan {
   uint64_t p, g, w, winv, ninv;
   uint32_t log2n, wbits, flags, passes, L1, L2, B, LT;
   int device;
-  bool lazy;
-  bool numeric;  // residues held in doubles (FP64 arithmetic), p < 2^49
+  int mode;      // the kernels' arithmetic mode: 1 lazy ranges, 0 below 2p, 2 doubles with p >= 2^49
+  bool numeric;  // residues held in doubles (FP64 arithmetic), p < 2^50
   void* dmem;
   size_t dbytes;
   const void *tw, *twi, *tlo, *thi, *tilo, *tihi, *tihin, *tihin1, *polyc, *passc;
@@ -352,7 +352,7 @@ int build_plan_tables(ntt_plan* pl) {
   pc.p = (T)p;
   pc.p2 = (T)(2 * p);
   pc.pinv = pinv_word;
-  pc.lazy = (T)(pl->lazy ? 1 : 0);
+  pc.lazy = (T)pl->mode;
   {
     const int lmax = (W == 32) ? 14 : 13;
     const int d = L > lmax ? L - lmax : 0;
@@ -434,7 +434,7 @@ int build_plan_tables(ntt_plan* pl) {
   sc.p = (T)p;
   sc.p2 = (T)(2 * p);
   sc.pinv = pinv_word;
-  sc.lazy = (T)(pl->lazy ? 1 : 0);
+  sc.lazy = (T)pl->mode;
   sc.ninv = pair_of<T>(pl->ninv, p);
   sc.sigma = pair_of<T>(sigma, p);
   sc.one = pair_of<T>(1, p);
@@ -525,9 +525,12 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
   if (log2n > 26) return fail(NTT_EUNSUPPORTED, "log2n = %u exceeds 26", log2n);
   if ((int)log2n > l)
     return fail(NTT_ENOROOT, "2^%u does not divide p - 1 (2-adic order %d)", log2n, l);
-  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE)) return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
-  if (numeric && p >= (1ull << 49))
-    return fail(NTT_EUNSUPPORTED, "FP64 residues need p < 2^49 (p = %llu)", (unsigned long long)p);
+  if (flags & ~(NTT_BITREV_OUT | NTT_BITREV_IN | NTT_VALIDATE | NTT_FP64))
+    return fail(NTT_EINVAL, "unknown flags 0x%x", flags);
+  if (flags & NTT_FP64) numeric = true;
+  if (numeric && p >= (1ull << 50))
+    return fail(NTT_EUNSUPPORTED, "FP64 residues need p < 2^50 (p = %llu)", (unsigned long long)p);
+  if (numeric && (flags & NTT_VALIDATE)) return fail(NTT_EUNSUPPORTED, "NTT_VALIDATE checks integer words, not doubles");
   if (g == 0) {
     g = smallest_generator(p);
   } else if (!generates(g, p, distinct_prime_factors(p - 1))) {
@@ -541,7 +544,8 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
   pl->flags = flags;
   pl->numeric = numeric;
   pl->wbits = (p < (1ull << 31) && !numeric) ? 32 : 64;
-  pl->lazy = numeric ? (p < (1ull << 48)) : (pl->wbits == 64 ? true : (p < (1ull << 30)));
+  // arithmetic mode of the kernels (kLazy 1, kSafe 0, kBand 2: see the butterflies)
+  pl->mode = numeric ? (p < (1ull << 48) ? 1 : p < (1ull << 49) ? 0 : 2) : (pl->wbits == 64 || p < (1ull << 30) ? 1 : 0);
   pl->w = powmod(g, (p - 1) >> log2n, p);
   pl->winv = invmod(pl->w, p);
   pl->ninv = invmod((1ull << log2n) % p, p);
@@ -554,6 +558,11 @@ int create_plan(ntt_plan** out, uint64_t p, uint64_t g, uint32_t log2n, uint32_t
     pl->passes = 2;
     pl->L2 = (uint32_t)tune_value(tune_key(product ? "psplit" : "split", wb, (int)log2n), pass_max_row_log2(wb));
     pl->L1 = log2n - pl->L2;
+  }
+  if (numeric && pl->passes > 1 && pl->L1 > 10) {
+    delete pl;
+    return fail(NTT_EUNSUPPORTED, "FP64 transforms of length 2^%u: columns of 2^%u words exceed 2^10", log2n,
+                log2n - (uint32_t)pass_max_row_log2(wb));
   }
   pl->B = (log2n + 1) / 2;
   if (hipGetDevice(&pl->device) != hipSuccess) {
@@ -696,7 +705,7 @@ int run_transform(const ntt_plan* pl, bool inverse, const void* in, void* out, s
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (dev != pl->device) return fail(NTT_EINVAL, "plan belongs to device %d, current device is %d", pl->device, dev);
-  const int wb = (int)pl->wbits;
+  const int wb = pl->numeric ? kWordF64 : (int)pl->wbits;  // kernel word code
   if (pl->flags & NTT_VALIDATE) {
     int rc = validate_range(wb, in, n, stride, batch, pl->p, stream);
     if (rc) return rc;
@@ -1162,6 +1171,7 @@ size_t single_product_ws(const ProductShape& s, int cus) {
 int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const void* b, size_t lb, void* c, size_t lc,
                           bool u16_inputs, void* ws, hipStream_t stream) {
   const int wb = (int)pl->wbits;
+  const int wk = pl->numeric ? kWordF64 : wb;  // kernel word code
   const size_t N = (size_t)1 << pl->log2n;
   unsigned char* w = (unsigned char*)ws;
   void* A = w;
@@ -1192,18 +1202,18 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   x.valid = la;
   x.scale = 0;
   x.rows = trunc ? lam : 0;
-  HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
+  HIP_TRY(launch_col_fwd(wk, x, L1, L2, stream));
   x.in = b;
   x.out = B;
   x.valid = lb;
   x.scale = trunc ? 3 : 1;  // the row inverse normalized by 2^-L2 when the columns take the inverse TFT
-  HIP_TRY(launch_col_fwd(wb, x, L1, L2, stream));
+  HIP_TRY(launch_col_fwd(wk, x, L1, L2, stream));
   x.in_u16 = 0;
   x.scale = 0;
   x.in = A;
   x.in2 = B;
   x.out = A;
-  HIP_TRY(launch_row_polymul(wb, x, L1, L2, stream));
+  HIP_TRY(launch_row_polymul(wk, x, L1, L2, stream));
   if (trunc) {
     TftArgs t = wb == 32 ? tft_args<uint32_t>(pl) : tft_args<uint64_t>(pl);
     t.in = A;
@@ -1222,7 +1232,7 @@ int run_multipass_product(const ntt_plan* pl, const void* a, size_t la, const vo
   x.in = A;
   x.out = c;
   x.valid = lc;
-  HIP_TRY(launch_col_inv(wb, x, L1, L2, stream));
+  HIP_TRY(launch_col_inv(wk, x, L1, L2, stream));
   return NTT_OK;
 }
 
@@ -1493,7 +1503,8 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
 }  // extern "C"
 
 // ---------------------------------------------------------------------------- reusable batches
-constexpr int kF64Group = -64;  // group word size of residues held in doubles
+constexpr int kF64Group = -64;      // group word size of residues held in doubles, p < 2^49
+constexpr int kF64BandGroup = -65;  // the same with 2^49 <= p < 2^50 (the kernels' band variant)
 struct ntt_batch {
   int device;
   void* ditems;  // device FusedItem array (owned)
@@ -1601,7 +1612,8 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
       fb.items = (const FusedItem*)bt->ditems + g.first;
       fb.park = workspace;
       fb.count = (int)g.count;
-      if (g.wb == kF64Group) HIP_TRY(launch_fused_f64(g.cls, fb, fused_grid(64, g.cls, g.count, bt->cus), stream));
+      if (g.wb == kF64Group || g.wb == kF64BandGroup)
+        HIP_TRY(launch_fused_f64(g.cls, g.wb == kF64BandGroup, fb, fused_grid(64, g.cls, g.count, bt->cus), stream));
       else HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), stream));
     }
     for (const auto& b : bt->big) {
@@ -2328,20 +2340,25 @@ int intmatmul_crt32(size_t n, const uint32_t* A, const uint32_t* B, size_t na, u
 // ============================================================================ FP64 residues
 namespace {
 
-// Shape checks of one FP64 product: p < 2^49 prime, transform within one workgroup.
+// Primes whose products over doubles take the kernels' band variant (2^49 <= p < 2^50:
+// multiplicands reduced before each product).
+bool f64_band(uint64_t p) { return p >= (1ull << 49); }
+
+// Shape checks of one FP64 product: p < 2^50 prime; transforms up to 2^15 in one
+// workgroup (fused), longer ones two-pass (columns of at most 2^10 words).
 int f64_shape(const ntt_polymul_desc& d, size_t i, ProductShape* s) {
-  if (d.p >= (1ull << 49))
-    return fail(NTT_EUNSUPPORTED, "descriptor %zu: FP64 residues need p < 2^49", i);
+  if (d.p >= (1ull << 50))
+    return fail(NTT_EUNSUPPORTED, "descriptor %zu: FP64 residues need p < 2^50", i);
   int rc = shape_of(d.p, d.la, d.lb, s);
   if (rc) {
     std::string m = g_last_error;
     return fail(rc, "descriptor %zu: %s", i, m.c_str());
   }
   s->wb = 64;
-  if (s->L > fused_max_log2n(64))
-    return fail(NTT_EUNSUPPORTED, "descriptor %zu: transform length 2^%d exceeds the FP64 limit 2^%d", i, s->L,
-                fused_max_log2n(64));
-  s->fused = true;
+  s->fused = s->L <= fused_max_log2n(64);
+  if (!s->fused && s->L - pass_max_row_log2(64) > 10)
+    return fail(NTT_EUNSUPPORTED, "descriptor %zu: FP64 transform length 2^%d exceeds 2^%d", i, s->L,
+                pass_max_row_log2(64) + 10);
   return NTT_OK;
 }
 
@@ -2373,20 +2390,33 @@ int polymul_f64_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t 
     bt->device = dev;
     bt->ditems = nullptr;
     std::vector<FusedItem> items;
-    for (int cls = 0; cls < 4; ++cls) {
-      const size_t first = items.size();
-      for (size_t i = 0; i < count; ++i) {
-        const ProductShape& s = shapes[i];
-        if (s.L < 0 || fused_class(64, s.L) != cls) continue;
-        ntt_plan* pl = nullptr;
-        int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
-        if (rc) {
-          delete bt;
-          return rc;
+    for (int band = 0; band < 2; ++band) {
+      for (int cls = 0; cls < 4; ++cls) {
+        const size_t first = items.size();
+        for (size_t i = 0; i < count; ++i) {
+          const ProductShape& s = shapes[i];
+          if (s.L < 0 || !s.fused || fused_class(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
+          ntt_plan* pl = nullptr;
+          int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+          if (rc) {
+            delete bt;
+            return rc;
+          }
+          items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
         }
-        items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+        if (items.size() > first) bt->groups.push_back({band ? kF64BandGroup : kF64Group, cls, first, items.size() - first});
       }
-      if (items.size() > first) bt->groups.push_back({kF64Group, cls, first, items.size() - first});
+    }
+    for (size_t i = 0; i < count; ++i) {
+      const ProductShape& s = shapes[i];
+      if (s.L < 0 || s.fused) continue;
+      ntt_plan* pl = nullptr;
+      int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+      if (rc) {
+        delete bt;
+        return rc;
+      }
+      bt->big.push_back({pl, d[i].a, d[i].b, d[i].c, d[i].la, d[i].lb, s.lc});
     }
     bt->cus = current_cus();
     bt->big_ws = batch_scratch(shapes, bt->cus, nullptr);
@@ -2451,24 +2481,27 @@ int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, 
     DeviceCtx* ctx = device_ctx(dev);
     std::vector<FusedItem> items;
     items.reserve(nfused);
-    struct Group { int cls; size_t first, count; };
+    struct Group { int cls; bool band; size_t first, count; };
     std::vector<Group> groups;
-    for (int cls = 0; cls < 4; ++cls) {
-      const size_t first = items.size();
-      for (size_t i = 0; i < count; ++i) {
-        const ProductShape& s = shapes[i];
-        if (s.L < 0 || fused_class(64, s.L) != cls) continue;
-        ntt_plan* pl = nullptr;
-        int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
-        if (rc) return rc;
-        items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+    for (int band = 0; band < 2; ++band) {
+      for (int cls = 0; cls < 4; ++cls) {
+        const size_t first = items.size();
+        for (size_t i = 0; i < count; ++i) {
+          const ProductShape& s = shapes[i];
+          if (s.L < 0 || !s.fused || fused_class(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
+          ntt_plan* pl = nullptr;
+          int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+          if (rc) return rc;
+          items.push_back(fused_item(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c));
+        }
+        if (items.size() > first) groups.push_back({cls, band != 0, first, items.size() - first});
       }
-      if (items.size() > first) groups.push_back({cls, first, items.size() - first});
     }
-    if (items.empty()) return ok();
     FusedItem* ditems = (FusedItem*)workspace;
-    int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
-    if (rc) return rc;
+    if (!items.empty()) {
+      int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
+      if (rc) return rc;
+    }
     void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
     for (const Group& g : groups) {
       FusedBatch fb;
@@ -2476,7 +2509,17 @@ int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, 
       fb.items = ditems + g.first;
       fb.park = bigws;
       fb.count = (int)g.count;
-      HIP_TRY(launch_fused_f64(g.cls, fb, fused_grid(64, g.cls, g.count, cus), stream));
+      HIP_TRY(launch_fused_f64(g.cls, g.band, fb, fused_grid(64, g.cls, g.count, cus), stream));
+    }
+    // two-pass products (transforms above 2^15), one after the other in the scratch
+    for (size_t i = 0; i < count; ++i) {
+      const ProductShape& s = shapes[i];
+      if (s.L < 0 || s.fused) continue;
+      ntt_plan* pl = nullptr;
+      int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
+      if (rc) return rc;
+      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, bigws, stream);
+      if (rc) return rc;
     }
     return ok();
   } catch (...) {
@@ -2495,7 +2538,7 @@ int ntt_arith_apply(int op, int word, uint64_t p, const void* x, const void* y, 
     if (op < NTT_ARITH_SHOUP || op > NTT_ARITH_GS) return fail(NTT_EINVAL, "unknown primitive %d", op);
     if (word != 32 && word != 64 && word != 0) return fail(NTT_EINVAL, "word must be 32, 64 or 0 (doubles)");
     if (p < 3 || !(p & 1)) return fail(NTT_EINVAL, "modulus must be odd and at least 3");
-    const uint64_t bound = word == 32 ? (1ull << 31) : word == 64 ? kMaxModulus : (1ull << 49);
+    const uint64_t bound = word == 32 ? (1ull << 31) : word == 64 ? kMaxModulus : (1ull << 50);
     if (p >= bound) return fail(NTT_EUNSUPPORTED, "modulus %llu beyond the word's bound", (unsigned long long)p);
     if (n == 0) return ok();
     const bool needs_y = op != NTT_ARITH_RED1 && op != NTT_ARITH_RED2;

@@ -8,6 +8,10 @@
 
 namespace nttgpu {
 
+// Word code of residues held in doubles (section 3's numeric types) in the launchers'
+// word_bits argument; 32 and 64 are the integer words.
+constexpr int kWordF64 = -64;
+
 struct FusedBatch {
   const FusedItem* items;  // device array, or NULL to use `single`
   void* park;              // workspace for parked partial results (fused_park_words per workgroup)
@@ -22,7 +26,7 @@ size_t fused_park_words(int word_bits, int cls);
 int fused_grid(int word_bits, int cls, size_t count, int cus);
 hipError_t launch_fused(int word_bits, int cls, const FusedBatch& batch, int grid, hipStream_t stream);
 // Residues held in doubles, p < 2^49 (classes and grids of the 64-bit word size).
-hipError_t launch_fused_f64(int cls, const FusedBatch& batch, int grid, hipStream_t stream);
+hipError_t launch_fused_f64(int cls, bool band, const FusedBatch& batch, int grid, hipStream_t stream);
 
 // Transform of `batch` vectors that fit one workgroup's LDS (log2n <= lds_max_log2n).
 struct LdsNttArgs {

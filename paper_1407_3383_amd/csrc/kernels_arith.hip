@@ -12,7 +12,7 @@ namespace nttgpu {
 
 namespace {
 
-template <typename T, int OP, bool LAZY>
+template <typename T, int OP, int LAZY>
 __global__ __launch_bounds__(256) void arith_apply_kernel(ArithArgs A, Arith<T> ar) {
   const T* x = (const T*)A.x;
   const T* y = (const T*)A.y;
@@ -50,16 +50,22 @@ __global__ __launch_bounds__(256) void arith_apply_kernel(ArithArgs A, Arith<T> 
 }
 
 template <typename T, int OP>
-hipError_t launch_op(const ArithArgs& a, const Arith<T>& ar, bool lazy, hipStream_t stream) {
+hipError_t launch_op(const ArithArgs& a, const Arith<T>& ar, int mode, hipStream_t stream) {
   const uint64_t blocks = (a.n + 255) / 256;
   const uint32_t grid = (uint32_t)(blocks < 4096 ? blocks : 4096);
-  if (lazy) hipLaunchKernelGGL((arith_apply_kernel<T, OP, true>), dim3(grid), dim3(256), 0, stream, a, ar);
-  else hipLaunchKernelGGL((arith_apply_kernel<T, OP, false>), dim3(grid), dim3(256), 0, stream, a, ar);
+  if (mode == kLazy) {
+    hipLaunchKernelGGL((arith_apply_kernel<T, OP, kLazy>), dim3(grid), dim3(256), 0, stream, a, ar);
+  } else if constexpr (std::is_same<T, double>::value) {
+    if (mode == kBand) hipLaunchKernelGGL((arith_apply_kernel<T, OP, kBand>), dim3(grid), dim3(256), 0, stream, a, ar);
+    else hipLaunchKernelGGL((arith_apply_kernel<T, OP, kSafe>), dim3(grid), dim3(256), 0, stream, a, ar);
+  } else {
+    hipLaunchKernelGGL((arith_apply_kernel<T, OP, kSafe>), dim3(grid), dim3(256), 0, stream, a, ar);
+  }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_word(const ArithArgs& a, const Arith<T>& ar, bool lazy, hipStream_t stream) {
+hipError_t launch_word(const ArithArgs& a, const Arith<T>& ar, int lazy, hipStream_t stream) {
   switch (a.op) {
     case NTT_ARITH_SHOUP: return launch_op<T, NTT_ARITH_SHOUP>(a, ar, lazy, stream);
     case NTT_ARITH_MONT: return launch_op<T, NTT_ARITH_MONT>(a, ar, lazy, stream);
@@ -80,20 +86,20 @@ hipError_t launch_arith_apply(const ArithArgs& a, hipStream_t stream) {
     ar.p = (uint32_t)a.p;
     ar.p2 = (uint32_t)(2 * a.p);
     ar.pinv = (uint32_t)a.pinv;
-    return launch_word<uint32_t>(a, ar, a.p < (1ull << 30), stream);
+    return launch_word<uint32_t>(a, ar, a.p < (1ull << 30) ? kLazy : kSafe, stream);
   }
   if (a.word == 64) {
     Arith<uint64_t> ar;
     ar.p = a.p;
     ar.p2 = 2 * a.p;
     ar.pinv = a.pinv;
-    return launch_word<uint64_t>(a, ar, true, stream);
+    return launch_word<uint64_t>(a, ar, kLazy, stream);
   }
   Arith<double> ar;
   ar.p = (double)a.p;
   ar.p2 = 2.0 * (double)a.p;
   ar.pinv = 1.0 / (double)a.p;
-  return launch_word<double>(a, ar, a.p < (1ull << 48), stream);
+  return launch_word<double>(a, ar, a.p < (1ull << 48) ? kLazy : a.p < (1ull << 49) ? kSafe : kBand, stream);
 }
 
 }  // namespace nttgpu

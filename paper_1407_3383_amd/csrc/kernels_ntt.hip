@@ -41,7 +41,7 @@ __device__ __forceinline__ Arith<T> arith_from(const PassConst<T>* pc) {
 }
 
 // ----------------------------------------------------------------------------- LDS-resident
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void lds_fwd_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -61,7 +61,7 @@ __device__ void lds_fwd_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   __syncthreads();
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void lds_inv_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -72,7 +72,7 @@ __device__ void lds_inv_body(const LdsNttArgs& A, T* s, uint64_t vec) {
   const TwPair<T> ninv = pc->ninv;
   for (int i = threadIdx.x; i < n; i += NT) {
     T x = ar.shoup(in[i], ninv.w, ninv.ws);  // n^-1 applied on the way in
-    if constexpr (!LAZY) x = ar.red1(x);
+    if constexpr (LAZY != kLazy) x = ar.red1(x);
     const int dst = A.bitrev ? i : (int)brev_bits((uint32_t)i, L);
     s[lidx(dst)] = x;
   }
@@ -87,15 +87,12 @@ __global__ __launch_bounds__(NT) void lds_ntt_kernel(LdsNttArgs A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
-  const bool lazy = pc->lazy != 0;
+  const int mode = (int)pc->lazy;
   for (uint64_t v = blockIdx.x; v < A.batch; v += gridDim.x) {
-    if (INV) {
-      if (lazy) lds_inv_body<T, true, NT>(A, s, v);
-      else lds_inv_body<T, false, NT>(A, s, v);
-    } else {
-      if (lazy) lds_fwd_body<T, true, NT>(A, s, v);
-      else lds_fwd_body<T, false, NT>(A, s, v);
-    }
+    with_mode<T>(mode, [&](auto m) {
+      if constexpr (INV) lds_inv_body<T, decltype(m)::value, NT>(A, s, v);
+      else lds_fwd_body<T, decltype(m)::value, NT>(A, s, v);
+    });
   }
 }
 
@@ -127,6 +124,11 @@ hipError_t launch_lds_ntt(int word_bits, bool inverse, const LdsNttArgs& a, hipS
     if (L <= 12) return launch_lds_cls<uint32_t, 256, 12>(inverse, a, stream);
     return launch_lds_cls<uint32_t, 1024, 14>(inverse, a, stream);
   }
+  if (word_bits == kWordF64) {
+    if (L <= 10) return launch_lds_cls<double, 64, 10>(inverse, a, stream);
+    if (L <= 12) return launch_lds_cls<double, 256, 12>(inverse, a, stream);
+    return launch_lds_cls<double, 1024, 13>(inverse, a, stream);
+  }
   if (L <= 10) return launch_lds_cls<uint64_t, 64, 10>(inverse, a, stream);
   if (L <= 12) return launch_lds_cls<uint64_t, 256, 12>(inverse, a, stream);
   return launch_lds_cls<uint64_t, 1024, 13>(inverse, a, stream);
@@ -143,7 +145,7 @@ int pass_col_tile_log2(int word_bits) { return word_bits == 32 ? kColTileLog32 :
 
 __device__ __forceinline__ int col_vs(int L1) { return lds_words(1 << L1) + 1; }  // odd: columns in different banks
 
-template <typename T, bool LAZY, int NT, int TILELOG, typename IN_T>
+template <typename T, int LAZY, int NT, int TILELOG, typename IN_T>
 __device__ void col_fwd_body(const PassArgs& A, T* s, uint64_t tile) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -175,7 +177,7 @@ __device__ void col_fwd_body(const PassArgs& A, T* s, uint64_t tile) {
   __syncthreads();
 }
 
-template <typename T, bool LAZY, int NT, int TILELOG>
+template <typename T, int LAZY, int NT, int TILELOG>
 __device__ void col_inv_body(const PassArgs& A, T* s, uint64_t tile) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -207,15 +209,12 @@ template <typename T, int NT, int TILELOG, bool INV, typename IN_T>
 __global__ __launch_bounds__(NT) void col_kernel(PassArgs A, uint64_t ntiles) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
-  const bool lazy = ((const PassConst<T>*)A.pc)->lazy != 0;
+  const int mode = (int)((const PassConst<T>*)A.pc)->lazy;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if constexpr (INV) {
-      if (lazy) col_inv_body<T, true, NT, TILELOG>(A, s, t);
-      else col_inv_body<T, false, NT, TILELOG>(A, s, t);
-    } else {
-      if (lazy) col_fwd_body<T, true, NT, TILELOG, IN_T>(A, s, t);
-      else col_fwd_body<T, false, NT, TILELOG, IN_T>(A, s, t);
-    }
+    with_mode<T>(mode, [&](auto m) {
+      if constexpr (INV) col_inv_body<T, decltype(m)::value, NT, TILELOG>(A, s, t);
+      else col_fwd_body<T, decltype(m)::value, NT, TILELOG, IN_T>(A, s, t);
+    });
   }
 }
 
@@ -229,7 +228,7 @@ __device__ __forceinline__ T twist(const Arith<T>& ar, T x, uint32_t e, int B, c
   return ar.shoup(ar.shoup(x, h.w, h.ws), l.w, l.ws);
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void row_fwd_body(const PassArgs& A, T* s, uint64_t rowid) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -249,7 +248,7 @@ __device__ void row_fwd_body(const PassArgs& A, T* s, uint64_t rowid) {
   __syncthreads();
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void row_inv_body(const PassArgs& A, T* s, uint64_t rowid) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -267,13 +266,13 @@ __device__ void row_inv_body(const PassArgs& A, T* s, uint64_t rowid) {
   const TwPair<T>* hi = (const TwPair<T>*)A.tihi;
   for (int j = threadIdx.x; j < n2; j += NT) {
     T x = twist(ar, s[lidx(j)], (uint32_t)j * R, B, lo, hi);
-    if constexpr (!LAZY) x = ar.red1(x);
+    if constexpr (LAZY != kLazy) x = ar.red1(x);
     out[j] = x;
   }
   __syncthreads();
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void row_polymul_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid) {
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
   const Arith<T> ar = arith_from(pc);
@@ -297,14 +296,14 @@ __device__ void row_polymul_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid
   fwd_lds<T, LAZY, NT, true>(ar, sa, sb, L2, 0, 0u, (const TwPair<T>*)A.tw);
   for (int j = threadIdx.x; j < n2; j += NT) {
     T x = sa[lidx(j)], y = sb[lidx(j)];
-    if constexpr (LAZY) {
+    if constexpr (LAZY == kLazy) {
       x = ar.red1(ar.red2(x));
     } else {
       x = ar.red1(x);
       y = ar.red1(y);
     }
     T z = ar.mont(x, y);
-    if constexpr (!LAZY) z = ar.red1(z);
+    if constexpr (LAZY != kLazy) z = ar.red1(z);
     sa[lidx(j)] = z;
   }
   __syncthreads();
@@ -313,7 +312,7 @@ __device__ void row_polymul_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid
   const TwPair<T>* ihi = (const TwPair<T>*)A.tihi;
   for (int j = threadIdx.x; j < n2; j += NT) {
     T x = twist(ar, sa[lidx(j)], (uint32_t)j * R, B, ilo, ihi);
-    if constexpr (!LAZY) x = ar.red1(x);
+    if constexpr (LAZY != kLazy) x = ar.red1(x);
     out[j] = x;
   }
   __syncthreads();
@@ -325,19 +324,15 @@ __global__ __launch_bounds__(NT) void row_kernel(PassArgs A, uint64_t nrows) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
   const PassConst<T>* pc = (const PassConst<T>*)A.pc;
-  const bool lazy = pc->lazy != 0;
+  const int mode = (int)pc->lazy;
   T* s2 = s + lds_words(1 << pc->L2);
   for (uint64_t t = blockIdx.x; t < nrows; t += gridDim.x) {
-    if constexpr (KIND == 0) {
-      if (lazy) row_fwd_body<T, true, NT>(A, s, t);
-      else row_fwd_body<T, false, NT>(A, s, t);
-    } else if constexpr (KIND == 1) {
-      if (lazy) row_inv_body<T, true, NT>(A, s, t);
-      else row_inv_body<T, false, NT>(A, s, t);
-    } else {
-      if (lazy) row_polymul_body<T, true, NT>(A, s, s2, t);
-      else row_polymul_body<T, false, NT>(A, s, s2, t);
-    }
+    with_mode<T>(mode, [&](auto m) {
+      constexpr int MODE = decltype(m)::value;
+      if constexpr (KIND == 0) row_fwd_body<T, MODE, NT>(A, s, t);
+      else if constexpr (KIND == 1) row_inv_body<T, MODE, NT>(A, s, t);
+      else row_polymul_body<T, MODE, NT>(A, s, s2, t);
+    });
   }
 }
 
@@ -457,6 +452,7 @@ static hipError_t launch_bitrev_t(const void* in, void* out, uint64_t is, uint64
 
 hipError_t launch_bitrev_permute(int word_bits, const void* in, void* out, uint64_t in_stride, uint64_t out_stride,
                                  uint32_t L, uint32_t batch, hipStream_t stream) {
+  // (doubles are moved as 64-bit patterns)
   if (word_bits == 32) return launch_bitrev_t<uint32_t>(in, out, in_stride, out_stride, L, batch, stream);
   return launch_bitrev_t<uint64_t>(in, out, in_stride, out_stride, L, batch, stream);
 }

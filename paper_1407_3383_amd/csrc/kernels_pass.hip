@@ -14,6 +14,8 @@
 //    entry-wise product and the inverse in one workgroup.
 #include <string.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "ntt_cols.hpp"
 #include "ntt_wave.hpp"
@@ -33,12 +35,15 @@ __device__ __forceinline__ Arith<T> arith_uni(const void* pcv) {
 }
 
 // x * G^j with G^j = w_N^e read as lo[e mod 2^B] * hi[e >> B]; any word x -> [0, 2p).
+// Residues held in doubles: each multiplicand is first reduced by one p (values below 2p,
+// or below 4p for p < 2^48, keep x w below 2^50 p as Function 16 needs).
 template <typename T>
 __device__ __forceinline__ T twist2(const Arith<T>& ar, T x, uint32_t e, int B, gcptr<TwPair<T>> lo,
                                     gcptr<TwPair<T>> hi) {
   const TwPair<T> h = ldtw<T>(hi + (e >> B));
   const TwPair<T> l = ldtw<T>(lo + (e & ((1u << B) - 1)));
-  return ar.shoup(ar.shoup(x, h.w, h.ws), l.w, l.ws);
+  if constexpr (std::is_same<T, double>::value) return ar.shoup(ar.red1(ar.shoup(ar.red1(x), h.w, h.ws)), l.w, l.ws);
+  else return ar.shoup(ar.shoup(x, h.w, h.ws), l.w, l.ws);
 }
 
 // Shoup companion floor(w 2^32 / p) of a residue w < p: the double estimate is within
@@ -84,7 +89,7 @@ __device__ __forceinline__ void row_factors(TwPair<uint32_t> (&D)[C], gcptr<TwPa
 }
 
 // Column pass for columns of 2^K words, K <= 10: tiles of C = 2^(TILELOG-K) columns.
-template <typename T, bool LAZY, int NT, int TILELOG, int K, bool INV, typename IN_T>
+template <typename T, int LAZY, int NT, int TILELOG, int K, bool INV, typename IN_T>
 __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, const Arith<T>& ar) {
   constexpr int LC0 = TILELOG - K;
   const int LC = LC0 < L2 ? LC0 : L2;
@@ -239,10 +244,11 @@ __global__ __launch_bounds__(NT, (NT == 1024 ? 8 : 4)) void col_wave_kernel(Pass
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* s = (T*)smem_raw;
   const Arith<T> ar = arith_uni<T>(A.pc);
-  const bool lazy = uni(gconst<PassConst<T>>(uni(A.pc))->lazy) != 0;
+  const int mode = (int)uni(gconst<PassConst<T>>(uni(A.pc))->lazy);
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    if (lazy) col_wave_body<T, true, NT, TILELOG, K, INV, IN_T>(A, s, t, L2, ar);
-    else col_wave_body<T, false, NT, TILELOG, K, INV, IN_T>(A, s, t, L2, ar);
+    with_mode<T>(mode, [&](auto m) {
+      col_wave_body<T, decltype(m)::value, NT, TILELOG, K, INV, IN_T>(A, s, t, L2, ar);
+    });
   }
 }
 
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(NT, (NT == 1024 ? 8 : 4)) void col_wave_kernel(Pass
 // KIND 0: forward (twist, transform); 1: inverse (transform, inverse twist);
 // 2: fused product of two operands (twist both, forward, entry-wise product,
 // inverse, inverse twist).  Rows of 2^M words, 10 <= M <= 14.
-template <typename T, bool LAZY, int NT, int M, int KIND>
+template <typename T, int LAZY, int NT, int M, int KIND>
 __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, const Arith<T>& ar) {
   constexpr int R = M - 10;
   constexpr int C = 1 << R;
@@ -344,14 +350,14 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           T xa = x[0][i], yb = x[1][i];
-          if constexpr (LAZY) {
+          if constexpr (LAZY == kLazy) {
             xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
           } else {
             xa = ar.red1(xa);
             yb = ar.red1(yb);
           }
           T z = ar.mont(xa, yb);  // (0, 2p); the Montgomery scale was applied to b
-          if constexpr (!LAZY) z = ar.red1(z);
+          if constexpr (LAZY != kLazy) z = ar.red1(z);
           x[0][i] = z;
         }
         inv_W<T, LAZY, M>(ar, sa, 0, 0u, twi, x[0]);
@@ -393,7 +399,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           T y = ar.shoup_u(ar.shoup(v[cc], V.w, V.ws), Di[cc].w, Di[cc].ws);
-          if constexpr (!LAZY) y = ar.red1(y);
+          if constexpr (LAZY != kLazy) y = ar.red1(y);
           out[q + 1024 * cc] = y;
         }
       } else {
@@ -401,7 +407,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
         for (int cc = 0; cc < C; ++cc) {
           const uint32_t j = (uint32_t)(q + 1024 * cc);
           T y = twist2(ar, v[cc], j * Rr, B, ilo, ihi);
-          if constexpr (!LAZY) y = ar.red1(y);
+          if constexpr (LAZY != kLazy) y = ar.red1(y);
           out[j] = y;
         }
       }
@@ -418,10 +424,9 @@ void row_wave_kernel(PassJobs J, uint64_t nrows) {
   T* sa = (T*)smem_raw;
   T* sb = sa + lds_words(1 << M);
   const Arith<T> ar = arith_uni<T>(A.pc);
-  const bool lazy = uni(gconst<PassConst<T>>(uni(A.pc))->lazy) != 0;
+  const int mode = (int)uni(gconst<PassConst<T>>(uni(A.pc))->lazy);
   for (uint64_t t = blockIdx.x; t < nrows; t += gridDim.x) {
-    if (lazy) row_wave_body<T, true, NT, M, KIND>(A, sa, sb, t, ar);
-    else row_wave_body<T, false, NT, M, KIND>(A, sa, sb, t, ar);
+    with_mode<T>(mode, [&](auto m) { row_wave_body<T, decltype(m)::value, NT, M, KIND>(A, sa, sb, t, ar); });
   }
 }
 
@@ -472,6 +477,10 @@ static PassJobs one_job(const PassArgs& a) {
 
 hipError_t launch_col_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
   if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
+  if (word_bits == kWordF64) {
+    if (L1 > 10) return hipErrorInvalidValue;  // the workgroup-round column kernels take integer words
+    return launch_col_wave<double, 512, 13, false, double>(a, L1, L2, stream);
+  }
   if (L1 > 10) {
     for (int i = 0; i < a.n; ++i) {
       hipError_t e = launch_col_fwd_rounds(word_bits, a.j[i], L1, L2, stream);
@@ -488,6 +497,10 @@ hipError_t launch_col_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2,
 
 hipError_t launch_col_inv_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
   if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
+  if (word_bits == kWordF64) {
+    if (L1 > 10) return hipErrorInvalidValue;
+    return launch_col_wave<double, 512, 13, true, double>(a, L1, L2, stream);
+  }
   if (L1 > 10) {
     for (int i = 0; i < a.n; ++i) {
       hipError_t e = launch_col_inv_rounds(word_bits, a.j[i], L1, L2, stream);
@@ -522,6 +535,11 @@ static hipError_t launch_row_wave(const PassJobs& a, int L1, hipStream_t stream)
 template <int KIND>
 static hipError_t launch_row_kind(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
   if (a.n < 1 || a.n > kMaxPassJobs) return hipErrorInvalidValue;
+  if (word_bits == kWordF64) {
+    if (L2 == 13) return launch_row_wave<double, 512, 13, KIND>(a, L1, stream);
+    if (L2 == 12) return launch_row_wave<double, 256, 12, KIND>(a, L1, stream);
+    return hipErrorInvalidValue;
+  }
   if (word_bits == 32) {
     if (L2 == 14) return launch_row_wave<uint32_t, 1024, 14, KIND>(a, L1, stream);
     if (L2 == 13) return launch_row_wave<uint32_t, 512, 13, KIND>(a, L1, stream);

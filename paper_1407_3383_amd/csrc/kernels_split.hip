@@ -28,7 +28,7 @@ __device__ __forceinline__ TwPair<T> root_pow(gcptr<TwPair<T>> t, uint32_t e, T 
   return x;
 }
 
-template <typename T, bool LAZY, int NT, int M, int D>
+template <typename T, int LAZY, int NT, int M, int D>
 __device__ void split_sub(const SplitArgs& A, T* sa, T* sb, const Arith<T>& ar) {
   constexpr int S = 1 << M;
   constexpr int K = 1 << D;  // fold terms at most
@@ -83,14 +83,14 @@ __device__ void split_sub(const SplitArgs& A, T* sa, T* sb, const Arith<T>& ar) 
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       T xa = x[0][i], yb = x[1][i];
-      if constexpr (LAZY) {
+      if constexpr (LAZY == kLazy) {
         xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
       } else {
         xa = ar.red1(xa);
         yb = ar.red1(yb);
       }
       T z = ar.mont(xa, yb);  // (0, 2p)
-      if constexpr (!LAZY) z = ar.red1(z);
+      if constexpr (LAZY != kLazy) z = ar.red1(z);
       x[0][i] = z;
     }
     inv_W<T, LAZY, M>(ar, sa, D, h, twi, x[0]);
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(NT) void polymul_split_kernel(SplitArgs A) {
 // The last D inverse stages across the 2^D partials (inverse of the fold's
 // first D forward stages): stage t = D-1 .. 0 pairs partials (i, i + 2^(D-1-t)) of
 // block `blk` with twiddle TWI[2^t + blk]; outputs k go to c[j + k S].
-template <typename T, bool LAZY, int D>
+template <typename T, int LAZY, int D>
 __device__ __forceinline__ void recombine_one(const SplitArgs& A, const Arith<T>& ar, uint64_t j, int M) {
   constexpr int K = 1 << D;
   const uint64_t S = 1ull << M;

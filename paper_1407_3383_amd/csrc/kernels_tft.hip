@@ -207,7 +207,7 @@ __device__ __forceinline__ T twist_e(const TftOps<T>& o, T x, uint64_t e, int B,
 // values, then y_j = (u_j + v_j) / 2, y_(j+half) = (u_j - v_j) / 2 (the twiddle of the
 // first stage is 1).  The universal tables' first 2^K entries are copied to LDS once;
 // each wave inverts its own columns.
-template <typename T, bool LAZY, int NT, int TILELOG, int K>
+template <typename T, int LAZY, int NT, int TILELOG, int K>
 __device__ void col_itft_body(const TftArgs& A, T* s, TwPair<T>* stw, TwPair<T>* stwi, uint64_t tile,
                               const TftOps<T>& o, gcptr<PassConst<T>> pc) {
   const int L2 = (int)A.L2;

@@ -8,7 +8,7 @@ namespace nttgpu {
 
 // Stages [T0, T0+R) of V vectors of 2^K words (K <= 10) at LDS stride vs, processed by
 // one wave: work items (vector, cluster) are spread over the 64 lanes.
-template <typename T, bool LAZY, bool INV, int R, int K, int T0, int V>
+template <typename T, int LAZY, bool INV, int R, int K, int T0, int V>
 __device__ __forceinline__ void vec_round(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> tw) {
   constexpr int C = 1 << R;
   constexpr int LS = K - T0 - R;
@@ -38,7 +38,7 @@ __device__ __forceinline__ void vec_round(const Arith<T>& ar, T* s, int vs, int 
   }
 }
 
-template <typename T, bool LAZY, int K, int V, int T0>
+template <typename T, int LAZY, int K, int V, int T0>
 __device__ __forceinline__ void vec_fwd_rounds(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> tw) {
   if constexpr (T0 < K) {
     constexpr int R = (T0 == 0 && (K & 3)) ? (K & 3) : 4;
@@ -48,7 +48,7 @@ __device__ __forceinline__ void vec_fwd_rounds(const Arith<T>& ar, T* s, int vs,
   }
 }
 
-template <typename T, bool LAZY, int K, int V, int T0END>
+template <typename T, int LAZY, int K, int V, int T0END>
 __device__ __forceinline__ void vec_inv_rounds(const Arith<T>& ar, T* s, int vs, int lane, gcptr<TwPair<T>> twi) {
   if constexpr (T0END > 0) {
     constexpr int R = (T0END == (K & 3)) ? (K & 3) : 4;

@@ -34,7 +34,7 @@ __device__ __forceinline__ int opaque_tid() {
 }
 __host__ __device__ constexpr int lds_words(int n) { return n + (n >> 5); }
 
-template <typename T, bool LAZY, int R, int NT, bool TWO>
+template <typename T, int LAZY, int R, int NT, bool TWO>
 __device__ __forceinline__ void fwd_round(const Arith<T>& ar, T* sa, T* sb, int m, int t0, int d, uint32_t h,
                                           const TwPair<T>* __restrict__ tw) {
   constexpr int C = 1 << R;
@@ -73,7 +73,7 @@ __device__ __forceinline__ void fwd_round(const Arith<T>& ar, T* sa, T* sb, int 
   }
 }
 
-template <typename T, bool LAZY, int R, int NT>
+template <typename T, int LAZY, int R, int NT>
 __device__ __forceinline__ void inv_round(const Arith<T>& ar, T* sa, int m, int t0, int d, uint32_t h,
                                           const TwPair<T>* __restrict__ twi) {
   constexpr int C = 1 << R;
@@ -107,7 +107,7 @@ __device__ __forceinline__ void inv_round(const Arith<T>& ar, T* sa, int m, int 
 
 // All m stages of the forward transform of the LDS vector(s); the first round takes
 // the m mod 4 leftover stages, the others radix 16.  Ends with a barrier.
-template <typename T, bool LAZY, int NT, bool TWO>
+template <typename T, int LAZY, int NT, bool TWO>
 __device__ void fwd_lds(const Arith<T>& ar, T* sa, T* sb, int m, int d, uint32_t h, const TwPair<T>* __restrict__ tw) {
   int t0 = 0;
   switch (m & 3) {
@@ -123,7 +123,7 @@ __device__ void fwd_lds(const Arith<T>& ar, T* sa, T* sb, int m, int d, uint32_t
 }
 
 // Inverse of fwd_lds's stage sequence (rounds in reverse order).  Ends with a barrier.
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void inv_lds(const Arith<T>& ar, T* sa, int m, int d, uint32_t h, const TwPair<T>* __restrict__ twi) {
   const int r0 = m & 3;
   for (int t0 = m - 4; t0 >= r0; t0 -= 4) {
@@ -142,7 +142,7 @@ __device__ void inv_lds(const Arith<T>& ar, T* sa, int m, int d, uint32_t h, con
 // The same stage sequence on `nvec` independent vectors of length 2^m stored at
 // LDS offsets v * vs (plain transforms: depth 0, block 0).  Work items are
 // (vector, cluster) pairs spread over the workgroup.
-template <typename T, bool LAZY, int R, int NT>
+template <typename T, int LAZY, int R, int NT>
 __device__ __forceinline__ void fwd_round_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, int t0,
                                                 const TwPair<T>* __restrict__ tw) {
   constexpr int C = 1 << R;
@@ -177,7 +177,7 @@ __device__ __forceinline__ void fwd_round_multi(const Arith<T>& ar, T* s, int vs
   }
 }
 
-template <typename T, bool LAZY, int R, int NT>
+template <typename T, int LAZY, int R, int NT>
 __device__ __forceinline__ void inv_round_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, int t0,
                                                 const TwPair<T>* __restrict__ twi) {
   constexpr int C = 1 << R;
@@ -212,7 +212,7 @@ __device__ __forceinline__ void inv_round_multi(const Arith<T>& ar, T* s, int vs
   }
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void fwd_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, const TwPair<T>* __restrict__ tw) {
   int t0 = 0;
   switch (m & 3) {
@@ -227,7 +227,7 @@ __device__ void fwd_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m,
   }
 }
 
-template <typename T, bool LAZY, int NT>
+template <typename T, int LAZY, int NT>
 __device__ void inv_lds_multi(const Arith<T>& ar, T* s, int vs, int nvec, int m, const TwPair<T>* __restrict__ twi) {
   const int r0 = m & 3;
   for (int t0 = m - 4; t0 >= r0; t0 -= 4) {
@@ -254,7 +254,7 @@ struct ClusterOff {
   static constexpr int off(int c) { return (c << LS) + ((c << LS) >> 5); }
 };
 
-template <typename T, bool LAZY, int R, int NT, int NV, int M, int T0>
+template <typename T, int LAZY, int R, int NT, int NV, int M, int T0>
 __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                              gcptr<TwPair<T>> tw) {
   constexpr int C = 1 << R;
@@ -300,7 +300,7 @@ __device__ __forceinline__ void fwd_round_ct(const Arith<T>& ar, T* const (&sv)[
   }
 }
 
-template <typename T, bool LAZY, int R, int NT, int M, int T0>
+template <typename T, int LAZY, int R, int NT, int M, int T0>
 __device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   constexpr int C = 1 << R;
   constexpr int LS = M - T0 - R;
@@ -340,7 +340,7 @@ __device__ __forceinline__ void inv_round_ct(const Arith<T>& ar, T* sa, int d, u
 }
 
 // Rounds of the forward transform: first the M mod 4 leftover stages, then radix 16.
-template <typename T, bool LAZY, int NT, int NV, int M, int T0>
+template <typename T, int LAZY, int NT, int NV, int M, int T0>
 __device__ __forceinline__ void fwd_rounds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                               gcptr<TwPair<T>> tw) {
   if constexpr (T0 < M) {
@@ -351,7 +351,7 @@ __device__ __forceinline__ void fwd_rounds_ct(const Arith<T>& ar, T* const (&sv)
   }
 }
 
-template <typename T, bool LAZY, int NT, int M, int T0END>
+template <typename T, int LAZY, int NT, int M, int T0END>
 __device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   // processes the round that ends at T0END (exclusive), then the earlier ones
   if constexpr (T0END > 0) {
@@ -363,13 +363,13 @@ __device__ __forceinline__ void inv_rounds_ct(const Arith<T>& ar, T* sa, int d, 
   }
 }
 
-template <typename T, bool LAZY, int NT, int NV, int M>
+template <typename T, int LAZY, int NT, int NV, int M>
 __device__ __forceinline__ void fwd_lds_ct(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                            gcptr<TwPair<T>> tw) {
   fwd_rounds_ct<T, LAZY, NT, NV, M, 0>(ar, sv, d, h, tw);
 }
 
-template <typename T, bool LAZY, int NT, int M>
+template <typename T, int LAZY, int NT, int M>
 __device__ __forceinline__ void inv_lds_ct(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   inv_rounds_ct<T, LAZY, NT, M, M>(ar, sa, d, h, twi);
 }

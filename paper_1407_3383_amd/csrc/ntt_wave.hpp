@@ -25,7 +25,7 @@ __device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 
 // Radix-2^R butterflies on a register cluster x[0 .. 2^R): cluster stage u pairs
 // (c, c + 2^(R-1-u)) with twiddle w[2^u - 1 + (c >> (R-u))].
-template <typename T, bool LAZY, int R, int NV, bool UNI = false>
+template <typename T, int LAZY, int R, int NV, bool UNI = false>
 __device__ __forceinline__ void cluster_fwd(const Arith<T>& ar, T (&x)[NV][1 << R], int off, const TwPair<T>* w) {
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -44,7 +44,7 @@ __device__ __forceinline__ void cluster_fwd(const Arith<T>& ar, T (&x)[NV][1 << 
   (void)off;
 }
 
-template <typename T, bool LAZY, int R, bool UNI = false>
+template <typename T, int LAZY, int R, bool UNI = false>
 __device__ __forceinline__ void cluster_inv(const Arith<T>& ar, T* x, const TwPair<T>* w) {
 #pragma unroll
   for (int u = R - 1; u >= 0; --u) {
@@ -82,7 +82,7 @@ __device__ __forceinline__ void cluster_twiddles(TwPair<T>* w, gcptr<TwPair<T>> 
 
 // ------------------------------------------------------------------ forward
 // Round G: local stages 0 .. M-11 on clusters {q + 1024 c}.  Ends with a barrier.
-template <typename T, bool LAZY, int NT, int NV, int M>
+template <typename T, int LAZY, int NT, int NV, int M>
 __device__ __forceinline__ void fwd_G(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                       gcptr<TwPair<T>> tw) {
   constexpr int R = M - 10;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void fwd_G(const Arith<T>& ar, T* const (&sv)[NV], in
 
 // Rounds W1..W3 of block B = wave id; the result stays in x[v][16] with
 // x[v][4 k + c] = element 1024 B + 4 (lane + 64 k) + c.
-template <typename T, bool LAZY, int NV, int M>
+template <typename T, int LAZY, int NV, int M>
 __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                       gcptr<TwPair<T>> tw, T (&x)[NV][16]) {
   const int tid = opaque_tid();
@@ -174,7 +174,7 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
 
 // ------------------------------------------------------------------ inverse
 // Rounds W3'..W1' from registers (layout of fwd_W), result stored to LDS.
-template <typename T, bool LAZY, int M>
+template <typename T, int LAZY, int M>
 __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi,
                                       T (&x)[16]) {
   const int tid = opaque_tid();
@@ -223,7 +223,7 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
 
 // Round G': local stages M-11 .. 0.  Starts with a barrier (the wave-local rounds
 // of every wave must have stored their blocks), ends with one.
-template <typename T, bool LAZY, int NT, int M>
+template <typename T, int LAZY, int NT, int M>
 __device__ __forceinline__ void inv_G(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi) {
   __syncthreads();
   constexpr int R = M - 10;

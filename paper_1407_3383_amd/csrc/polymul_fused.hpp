@@ -21,7 +21,7 @@
 namespace nttgpu {
 
 // PM = 0: partials in registers; PM = 1: partials in the workspace slice `park`.
-template <typename T, bool LAZY, int NT, int M, int MAXD, int PM>
+template <typename T, int LAZY, int NT, int M, int MAXD, int PM>
 __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic) {
   const gptr<T> park = gmut<T>(park_generic);
   const PolyConst<T>* __restrict__ pc = (const PolyConst<T>*)it.cst;
@@ -102,14 +102,14 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           T xa = x[0][i], yb = x[1][i];
-          if constexpr (LAZY) {
+          if constexpr (LAZY == kLazy) {
             xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
           } else {
             xa = ar.red1(xa);
             yb = ar.red1(yb);
           }
           T z = ar.mont(xa, yb);  // (0, 2p)
-          if constexpr (!LAZY) z = ar.red1(z);
+          if constexpr (LAZY != kLazy) z = ar.red1(z);
           x[0][i] = z;
         }
         inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
@@ -123,14 +123,14 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
         const int j = tp + k0 * NT;
         if (j < S) {
           T x = sa[lidx(j)], y = sb[lidx(j)];
-          if constexpr (LAZY) {
+          if constexpr (LAZY == kLazy) {
             x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
           } else {
             x = ar.red1(x);
             y = ar.red1(y);
           }
           T z = ar.mont(x, y);  // (0, 2p)
-          if constexpr (!LAZY) z = ar.red1(z);
+          if constexpr (LAZY != kLazy) z = ar.red1(z);
           sa[lidx(j)] = z;
         }
       }
@@ -234,7 +234,7 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
 //     product in registers and the wave-local inverse rounds.
 // G'(h-1) and G(h) touch the same elements of the same thread, so no barrier
 // separates them, and the fold loads are in flight while G' computes.
-template <typename T, bool LAZY, int NT, int M, int MAXD>
+template <typename T, int LAZY, int NT, int M, int MAXD>
 __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa, T* sb, T* park_generic) {
   static_assert(M >= 10 && M <= 14, "wave-local sub-problems span 2^10 .. 2^14 words");
   // the descriptor is the same for the whole workgroup: keep it in scalar registers
@@ -384,14 +384,14 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         T xa = x[0][i], yb = x[1][i];
-        if constexpr (LAZY) {
+        if constexpr (LAZY == kLazy) {
           xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
         } else {
           xa = ar.red1(xa);
           yb = ar.red1(yb);
         }
         T z = ar.mont(xa, yb);  // (0, 2p)
-        if constexpr (!LAZY) z = ar.red1(z);
+        if constexpr (LAZY != kLazy) z = ar.red1(z);
         x[0][i] = z;
       }
       inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
@@ -471,39 +471,47 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   }
 }
 
-template <typename T, int NT, int M, int MAXD, int PM>
+// The arithmetic mode of the item's prime: kLazy or kSafe read from its constants, or
+// kBand in the kernels instantiated for residues in doubles with 2^49 <= p < 2^50 (a
+// kernel of their own, so that the extra reductions do not weigh on the register
+// allocation of the other two modes).
+template <typename T, int NT, int M, int MAXD, int PM, bool BAND>
 __device__ __forceinline__ void polymul_dispatch_lazy(const FusedItem& it, T* sa, T* sb, T* park) {
   const PolyConst<T>* pc = (const PolyConst<T>*)it.cst;
-  if constexpr (M >= 10 && PM == 1) {
-    if (uni(gconst<PolyConst<T>>(uni(it.cst))->lazy)) polymul_item_wave<T, true, NT, M, MAXD>(it, sa, sb, park);
-    else polymul_item_wave<T, false, NT, M, MAXD>(it, sa, sb, park);
+  if constexpr (BAND) {
+    if constexpr (M >= 10 && PM == 1) polymul_item_wave<T, kBand, NT, M, MAXD>(it, sa, sb, park);
+    else polymul_item<T, kBand, NT, M, MAXD, PM>(it, sa, sb, park);
+  } else if constexpr (M >= 10 && PM == 1) {
+    if (uni(gconst<PolyConst<T>>(uni(it.cst))->lazy)) polymul_item_wave<T, kLazy, NT, M, MAXD>(it, sa, sb, park);
+    else polymul_item_wave<T, kSafe, NT, M, MAXD>(it, sa, sb, park);
   } else {
-    if (pc->lazy) polymul_item<T, true, NT, M, MAXD, PM>(it, sa, sb, park);
-    else polymul_item<T, false, NT, M, MAXD, PM>(it, sa, sb, park);
+    if (pc->lazy) polymul_item<T, kLazy, NT, M, MAXD, PM>(it, sa, sb, park);
+    else polymul_item<T, kSafe, NT, M, MAXD, PM>(it, sa, sb, park);
   }
 }
 
 // Sub-problem size 2^M for a product of transform length 2^L in a class whose
 // largest sub-problem is 2^LOGS and smallest transform 2^LMIN.
-template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM, bool BAND>
 __device__ __forceinline__ void polymul_dispatch(const FusedItem& it, T* sa, T* sb, T* park) {
   const int L = (int)it.log2n;
   const int m = L < LOGS ? L : LOGS;
   if constexpr (LOGS - LMIN >= 10) {
-    if (m <= LOGS - 10) { polymul_dispatch_lazy<T, NT, LOGS - 10, MAXD, PM>(it, sa, sb, park); return; }
+    if (m <= LOGS - 10) { polymul_dispatch_lazy<T, NT, LOGS - 10, MAXD, PM, BAND>(it, sa, sb, park); return; }
   }
 #define NTT_CASE(K)                                                                    \
   if constexpr (LOGS - LMIN >= K) {                                                    \
-    if (m == LOGS - K) { polymul_dispatch_lazy<T, NT, LOGS - K, MAXD, PM>(it, sa, sb, park); return; } \
+    if (m == LOGS - K) { polymul_dispatch_lazy<T, NT, LOGS - K, MAXD, PM, BAND>(it, sa, sb, park); return; } \
   }
   NTT_CASE(9) NTT_CASE(8) NTT_CASE(7) NTT_CASE(6) NTT_CASE(5) NTT_CASE(4) NTT_CASE(3) NTT_CASE(2) NTT_CASE(1)
 #undef NTT_CASE
-  polymul_dispatch_lazy<T, NT, LOGS, MAXD, PM>(it, sa, sb, park);
+  polymul_dispatch_lazy<T, NT, LOGS, MAXD, PM, BAND>(it, sa, sb, park);
 }
 
 // Workgroup w serves items w, w + G, w + 2G, ...; with PM = 1 it parks partial
-// results in its own workspace slice of 3 * 2^LOGS words.
-template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
+// results in its own workspace slice of 3 * 2^LOGS words.  BAND: every item is a
+// product over doubles with 2^49 <= p < 2^50.
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM, bool BAND = false>
 __global__ __launch_bounds__(NT) void polymul_fused_kernel(FusedBatch batch) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
@@ -511,14 +519,14 @@ __global__ __launch_bounds__(NT) void polymul_fused_kernel(FusedBatch batch) {
   T* park = PM == 1 ? (T*)batch.park + (size_t)blockIdx.x * 3 * ((size_t)1 << LOGS) : nullptr;
   for (int i = blockIdx.x; i < batch.count; i += gridDim.x) {
     const FusedItem it = batch.items ? batch.items[i] : batch.single;
-    polymul_dispatch<T, NT, LOGS, LMIN, MAXD, PM>(it, sa, sb, park);
+    polymul_dispatch<T, NT, LOGS, LMIN, MAXD, PM, BAND>(it, sa, sb, park);
   }
 }
 
-template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM>
+template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM, bool BAND = false>
 hipError_t launch_fused_cls(const FusedBatch& batch, int grid, hipStream_t stream) {
   const size_t lds = 2 * (size_t)lds_words(1 << LOGS) * sizeof(T);
-  auto k = polymul_fused_kernel<T, NT, LOGS, LMIN, MAXD, PM>;
+  auto k = polymul_fused_kernel<T, NT, LOGS, LMIN, MAXD, PM, BAND>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(grid), dim3(NT), lds, stream, batch);

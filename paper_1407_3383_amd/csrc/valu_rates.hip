@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void rate_fma64_kernel(uint32_t* out, int iter
 
 // The library's butterflies on registers: 8 pairs per thread, 16 butterflies per
 // pair and iteration, twiddle in scalar registers (the UNI forms).
-template <bool GS, bool LAZY>
+template <bool GS, int LAZY>
 __global__ __launch_bounds__(256) void rate_bfly_kernel(uint32_t* out, int iters, uint32_t p, uint32_t pinv,
                                                         uint32_t w, uint32_t ws) {
   const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;

@@ -20,6 +20,7 @@ CFG_POLYMUL_BATCH = 1     # 1024 polymuls mod 2013265921, length 2^15 operands
 CFG_NTT_2_24 = 2          # one length-2^24 transform mod 469762049
 CFG_INTMUL = 3            # 2^21 x 2^21 16-bit-limb integer product
 CFG_SERVE = 4             # serving mix
+CFG_FFT = 5               # transforms of length 2^8..2^20, 2^24 words per call
 CFG_TEST = 99             # ad-hoc test inputs
 
 P_998 = 998244353         # 119 * 2^23 + 1

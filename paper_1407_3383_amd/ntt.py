@@ -36,6 +36,7 @@ NTT_EUNSUPPORTED = -7
 NTT_BITREV_OUT = 1
 NTT_BITREV_IN = 2
 NTT_VALIDATE = 4
+NTT_FP64 = 8
 
 # Every symbol the header declares.
 EXPORTS = (

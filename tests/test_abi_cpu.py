@@ -192,11 +192,17 @@ def test_polymatmul_argument_errors_and_sizes(lib):
 def test_f64_batch_argument_errors(lib):
     one = 16
     descs = (ntt.PolymulDesc * 1)()
-    descs[0] = ntt.PolymulDesc(63 * 2 ** 44 + 1, one, 8, one, 8, one)       # p >= 2^49
+    descs[0] = ntt.PolymulDesc(ntt.find_prime(50, 20), one, 8, one, 8, one)  # 2^49 < p < 2^50
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_ENOMEM
+    p49 = ntt.find_prime(49, 20)
+    p49b = ntt.find_prime(49, 25)
+    descs[0] = ntt.PolymulDesc(p49b, one, 1 << 23, one, 1 << 23, one)        # transform 2^24
     assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EUNSUPPORTED
     assert lib.polymul_f64_batch_workspace_bytes(descs, 1) == 0
-    p49 = ntt.find_prime(49, 20)
-    descs[0] = ntt.PolymulDesc(p49, one, 1 << 15, one, 1 << 15, one)         # transform 2^16
+    descs[0] = ntt.PolymulDesc(p49, one, 1 << 15, one, 1 << 15, one)         # transform 2^16: two-pass
+    assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_ENOMEM
+    assert lib.polymul_f64_batch_workspace_bytes(descs, 1) >= (2 * 8) << 16
+    descs[0] = ntt.PolymulDesc(1 << 50, one, 8, one, 8, one)                 # p >= 2^50
     assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_EUNSUPPORTED
     descs[0] = ntt.PolymulDesc(p49, one, 8, one, 8, one)
     assert lib.polymul_f64_batch(descs, 1, None, 0, None) == ntt.NTT_ENOMEM
@@ -225,7 +231,7 @@ def test_arith_apply_argument_errors(lib):
     assert lib.ntt_arith_apply(0, 16, 998244353, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EINVAL
     assert lib.ntt_arith_apply(0, 32, 998244352, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EINVAL
     assert lib.ntt_arith_apply(0, 32, 2 ** 31 + 11, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EUNSUPPORTED
-    assert lib.ntt_arith_apply(0, 0, 63 * 2 ** 44 + 1, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EUNSUPPORTED
+    assert lib.ntt_arith_apply(0, 0, 2 ** 50 + 1, one, one, one, 0, 0, one, 8, None) == ntt.NTT_EUNSUPPORTED
     assert lib.ntt_arith_apply(0, 32, 998244353, one, one, None, 0, 0, one, 8, None) == ntt.NTT_EINVAL
     assert lib.ntt_arith_apply(2, 64, 998244353, ctypes.c_void_p(20), None, None, 0, 0, one, 8, None) == ntt.NTT_EINVAL
     assert lib.ntt_arith_apply(2, 64, 998244353, one, None, None, 0, 0, one, 0, None) == ntt.NTT_OK
