@@ -199,11 +199,14 @@ int polymul_modp_noalloc(uint64_t p, const void* a, size_t la, const void* b, si
 /* Device scratch for polymul_modp_batch on these descriptors. */
 size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
 
-/* All `count` products in as few launches as the sizes allow: every descriptor
+/* All `count` products in as few launches as the sizes allow: the descriptors
  * whose transform fits one workgroup (N <= 2^16 for 32-bit, 2^15 for 64-bit
- * primes) is served by ONE persistent fused launch (fold, forward x2, entry-wise
- * product, inverse, combine) whatever its prime and length (section 2.2, Remark 6:
- * several moduli in one vector launch); larger ones run the multi-pass path.
+ * primes) are grouped by word size and size class (the classes differ in
+ * workgroup size and LDS), and each group is ONE persistent fused launch (fold,
+ * forward x2, entry-wise product, inverse, combine) whatever the primes and
+ * lengths of its products (section 2.2, Remark 6: several moduli in one vector
+ * launch); the groups' launches run one after another on hip_stream, then the
+ * larger products run the multi-pass path one after another.
  * `d` is a HOST array; its content is copied into the workspace.
  * Errors as polymul_modp, checked for every descriptor before anything runs. */
 int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes,
