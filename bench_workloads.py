@@ -283,8 +283,11 @@ def run_polymatrix(args):
 
 
 def run_serve(args):
-    """Serving mix: capacity with everything queued at t = 0, then Poisson arrivals
-    at 0.5, 0.8 and 0.95 of that capacity; p50/p99 latency and throughput."""
+    """Serving mix as the caller sees it: every product delivered to the request's host
+    buffer.  Capacity with everything queued at t = 0, then Poisson arrivals at 0.5, 0.8
+    and 0.95 of that capacity (p50/p99 latency from arrival to the product in host
+    memory); the same with products left in device memory as a secondary figure."""
+    import numpy as np
     import torch
 
     from paper_1407_3383_amd import inputs, ntt, serve
@@ -295,69 +298,94 @@ def run_serve(args):
     _log("serve: generating %d requests" % n)
     ops = [inputs.serve_operands(p, L, rid) for (p, L, rid) in specs]
     total_bfly = sum(serve.butterflies(L, L) for (_, L, _) in specs)
+    bufs = {}  # result buffers by request id, allocated and touched once (the caller's buffers)
 
     def make(arrivals):
-        return [serve.Request(rid, p, a, b, arrival=float(t))
+        reqs = [serve.Request(rid, p, a, b, arrival=float(t))
                 for (p, L, rid), (a, b), t in zip(specs, ops, arrivals)]
+        for r in reqs:
+            r.result = bufs.get(r.rid)
+        return reqs
+
+    def keep(reqs):
+        for r in reqs:
+            if isinstance(r.result, np.ndarray):
+                bufs[r.rid] = r.result
 
     budget = 8 << 30
-    # comparisons on the first m requests (the Python loop pins every queued request's
-    # operands at once; the copy-back run holds every product in host memory)
+    Server = serve.NativeServer
+
+    def saturated(back, count):
+        reqs = make([0.0] * count)
+        srv = Server(budget, streams=4, max_batch=64, keep_results=back)
+        wall = srv.run(reqs, realtime=False)
+        srv.close()
+        keep(reqs)
+        return wall, srv
+
+    def poisson(back, cap_rps, frac, reqs_fn=None):
+        arr = inputs.poisson_arrivals(n, frac * cap_rps, int(frac * 100))
+        reqs = (reqs_fn or make)(arr)
+        srv = Server(budget, streams=4, max_batch=64, keep_results=back)
+        w = srv.run(reqs, realtime=True)
+        srv.close()
+        keep(reqs)
+        return w, srv
+
+    # comparisons on the first m requests: the Python loop (which pins every queued
+    # request's operands at once) and products copied straight into page-locked buffers
     m = min(n, 1000)
-    # the Python request loop, for comparison (everything queued at t = 0)
     warm = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
     warm.run(make([0.0] * m), realtime=False)
     pysat = serve.Server(budget, streams=4, max_batch=64, keep_results=False)
     pywall = pysat.run(make([0.0] * m), realtime=False)
     _log("serve: python loop %.1f req/s over %d requests" % (m / pywall, m))
-    # the native request loop (ntt_server_*): the measured one
-    Server = serve.NativeServer
-    warm = Server(budget, streams=4, max_batch=64, keep_results=False)
-    warm.run(make([0.0] * n), realtime=False)
-    warm.close()
-    sat = Server(budget, streams=4, max_batch=64, keep_results=False)
-    wall = sat.run(make([0.0] * n), realtime=False)
-    sat.close()
+    # the native loop (ntt_server_*), products copied back: warm-up (allocates and touches
+    # the result buffers), then the measured run
+    saturated(True, n)
+    wall, sat = saturated(True, n)
     capacity = n / wall
-    _log("serve: native loop %.1f req/s over %d requests" % (capacity, n))
-    # the same with every product copied back to host memory
-    back = Server(budget, streams=4, max_batch=64, keep_results=True)
-    wall_back = back.run(make([0.0] * m), realtime=False)
-    back.close()
+    _log("serve: native loop with copy-back %.1f req/s over %d requests" % (capacity, n))
+    wall_dev, sat_dev = saturated(False, n)
+    capacity_dev = n / wall_dev
+    _log("serve: native loop, products left on the device %.1f req/s" % capacity_dev)
     pin = Server(budget, streams=4, max_batch=64, keep_results=True, pinned_results=True)
     wall_pin = pin.run(make([0.0] * m), realtime=False)
     pin.close()
-    # native loop on the same m requests (the comparisons' own reference)
-    sub = Server(budget, streams=4, max_batch=64, keep_results=False)
-    wall_sub = sub.run(make([0.0] * m), realtime=False)
-    sub.close()
-    out = {"metric": "serving mix: p50/p99 latency and throughput", "value": round(capacity, 2), "unit": "requests/s",
+    wall_sub, sub = saturated(True, m)
+    out = {"metric": "serving mix with every product copied back to host memory: p50/p99 latency and throughput",
+           "value": round(capacity, 2), "unit": "requests/s",
            "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
-           "config": {"workload": "%d polymul requests, L = floor(2^U(8,20)), p uniform over {998244353, 2013265921, %d}" % (n, p62),
+           "config": {"workload": "%d polymul requests, L = floor(2^U(8,20)), p uniform over {998244353, 2013265921, %d}, "
+                                  "host operands in, host products out" % (n, p62),
                       "hbm_budget_bytes": budget, "streams": 4, "loop": "native (ntt_server_*)"},
            "saturated": {"requests_per_s": round(capacity, 2), "Gbfly_per_s": round(total_bfly / wall / 1e9, 2),
                          **serve.latency_stats(sat.completed)},
+           "saturated_products_left_on_device": {"requests_per_s": round(capacity_dev, 2),
+                                                 "Gbfly_per_s": round(total_bfly / wall_dev / 1e9, 2),
+                                                 **serve.latency_stats(sat_dev.completed)},
            "first_%d_requests" % m: {
-               "native_saturated": {"requests_per_s": round(m / wall_sub, 2), **serve.latency_stats(sub.completed)},
-               "native_with_copy_back": {"requests_per_s": round(m / wall_back, 2), **serve.latency_stats(back.completed)},
+               "native_with_copy_back": {"requests_per_s": round(m / wall_sub, 2), **serve.latency_stats(sub.completed)},
                "native_with_copy_back_to_pinned": {"requests_per_s": round(m / wall_pin, 2),
                                                    **serve.latency_stats(pin.completed)},
-               "python_loop_saturated": {"requests_per_s": round(m / pywall, 2), **serve.latency_stats(pysat.completed)}}}
-    levels = {}
+               "python_loop_products_left_on_device": {"requests_per_s": round(m / pywall, 2),
+                                                       **serve.latency_stats(pysat.completed)}}}
+    levels, levels_dev = {}, {}
     for frac in (0.5, 0.8, 0.95):
-        arr = inputs.poisson_arrivals(n, frac * capacity, int(frac * 100))
-        srv = Server(budget, streams=4, max_batch=64, keep_results=False)
-        w = srv.run(make(arr), realtime=True)
-        srv.close()
-        st = serve.latency_stats(srv.completed)
-        levels[str(frac)] = {"offered_rps": round(frac * capacity, 2), "achieved_rps": round(n / w, 2),
-                             "Gbfly_per_s": round(total_bfly / w / 1e9, 2), "max_inflight_batches": srv.max_inflight_batches,
-                             **st}
-        _log("serve at %.2f x capacity: p50 %.3f ms, p99 %.3f ms" % (frac, st["p50_ms"], st["p99_ms"]))
+        for back, cap_rps, dst in ((True, capacity, levels), (False, capacity_dev, levels_dev)):
+            w, srv = poisson(back, cap_rps, frac)
+            st = serve.latency_stats(srv.completed)
+            dst[str(frac)] = {"offered_rps": round(frac * cap_rps, 2), "achieved_rps": round(n / w, 2),
+                              "Gbfly_per_s": round(total_bfly / w / 1e9, 2),
+                              "max_inflight_batches": srv.max_inflight_batches, **st}
+            _log("serve at %.2f x capacity (%s): p50 %.3f ms, p99 %.3f ms"
+                 % (frac, "copy-back" if back else "device", st["p50_ms"], st["p99_ms"]))
     out["poisson"] = levels
+    out["poisson_products_left_on_device"] = levels_dev
+
     # the same stream with every 10th request an integer product of L 16-bit limbs
-    # (three-prime transform, CRT and carries), at 0.8 of the polynomial capacity
+    # (three-prime transform, CRT and carries), at 0.8 of the capacity, copied back
     def make_mixed(arrivals):
         reqs = make(arrivals)
         for k in range(0, n, 10):
@@ -367,13 +395,10 @@ def run_serve(args):
             b = inputs.limbs16(L, inputs.CFG_SERVE, r.rid, 1)
             reqs[k] = serve.Request(r.rid, 0, a, b, arrival=r.arrival, kind="int")
         return reqs
-    warm = Server(budget, streams=4, max_batch=64, keep_results=False)
+    warm = Server(budget, streams=4, max_batch=64, keep_results=True)
     warm.run(make_mixed([0.0] * n), realtime=False)
     warm.close()
-    arr = inputs.poisson_arrivals(n, 0.8 * capacity, 80)
-    srv = Server(budget, streams=4, max_batch=64, keep_results=False)
-    w = srv.run(make_mixed(arr), realtime=True)
-    srv.close()
+    w, srv = poisson(True, capacity, 0.8, make_mixed)
     st = serve.latency_stats(srv.completed)
     ints = [r for r in srv.completed if r.kind == "int"]
     out["with_integer_products"] = {"share": 0.1, "offered_rps": round(0.8 * capacity, 2), "achieved_rps": round(n / w, 2),

@@ -245,9 +245,12 @@ int polymul_batch_destroy(ntt_batch* batch);
  *                     2^(L-d) points on 2^d workgroups at once, then recombines them
  *                     (latency path; workspace N words): d = 1, 2 or 3 with
  *                     10 <= L - d <= 13 (32-bit) / 12 (64-bit), or 0 (default: off)
- *   "server.copy_threads"  host threads (besides the caller) that copy operands into and
- *                     products out of a serving loop's staging: 0 .. 63 (default 7), read
- *                     by ntt_server_create
+ *   "server.copy_threads"  host threads that copy operands into and products out of a
+ *                     serving loop's staging: 0 .. 63 (default 7; 0: the driving thread
+ *                     copies), read by ntt_server_create
+ *   "server.batches_per_stream"  batches a serving loop keeps in flight per stream, each
+ *                     with its own staging block: 1 .. 8 (default 2), read by
+ *                     ntt_server_create
  *   "tft.rows.w32", "tft.rows.w64"  1: two-pass products run only the first
  *                     ceil(lc / 2^row_log2) rows of their transforms (section 5.1's TFT)
  *                     and invert the columns by the inverse TFT; 0 (default): full-length
@@ -312,7 +315,9 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
  * budget has room: consecutive polynomial requests form one polymul_modp_batch call,
  * an integer product one intmul_crt call, each batch with one upload and one download
  * through page-locked staging, on one of `streams` streams (default priority).
- * Batches in flight overlap on the device (at most 2 per stream).  c == NULL: the
+ * Batches in flight overlap on the device (at most 2 per stream by default).  The
+ * host copies into and out of staging run on the server's copy threads while the
+ * device works; ntt_server_progress itself never waits for them.  c == NULL: the
  * product is computed but not copied back; c in page-locked host memory (hipHostMalloc,
  * torch pin_memory): the product is copied there directly by DMA, without staging.  The server owns one device buffer of
  * hbm_budget bytes (the arena) and its page-locked staging (32 MiB per batch in

@@ -83,6 +83,7 @@ bool tune_valid(const std::string& key, int64_t v) {
   }
   if (sscanf(key.c_str(), "tft.rows.w%d%c", &w, &tail) == 1) return (w == 32 || w == 64) && (v == 0 || v == 1);
   if (key == "server.copy_threads") return v >= 0 && v <= 63;
+  if (key == "server.batches_per_stream") return v >= 1 && v <= 8;
   if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
     if (w == 32) return v >= 14 && v <= 16;
     if (w == 64) return v >= 13 && v <= 15;

@@ -1,17 +1,19 @@
 // Native serving loop: continuous batching of polynomial and integer products by HBM
 // budget (the batching of section 2.2's Remark 6 applied to a request stream).
 //
-// Requests carry host operands.  progress() completes finished batches (their results
-// are copied back to the requests' host buffers), then admits pending requests in
-// arrival order while the device arena has room: consecutive polynomial requests form
-// one batched call (polymul_modp_batch: one fused launch per size class), an integer
-// product is one intmul_crt call.  Each batch owns one arena block [operands | products
-// | workspace] and one page-locked staging block [operands | products], so a batch costs
-// one upload, one library call and one download, all asynchronous on one of the
-// server's streams, followed by an event.  Batches on different streams overlap on the
-// device.  The host copies into and out of the staging blocks run on a small pool of
-// copy threads (one thread's memcpy is well below the host's memory bandwidth and would
-// bound the loop).  Not thread-safe: one host thread drives a server.
+// Requests carry host operands.  progress() admits pending requests in arrival order
+// while the device arena has room: consecutive polynomial requests form one batched call
+// (polymul_modp_batch: one fused launch per size class), an integer product is one
+// intmul_crt call.  Each batch owns one arena block [operands | products | workspace]
+// and one page-locked staging block [operands | products], so a batch costs one upload,
+// one library call and one download, all asynchronous on one of the server's streams,
+// followed by an event.  Batches on different streams overlap on the device.  The host
+// copies into and out of the staging blocks run on a pool of copy threads, and the
+// driving thread never waits for them: a batch's operands are copied while earlier
+// batches compute, it is enqueued by the first progress() call after its copy, and its
+// products are copied out while later batches compute (one thread's memcpy is well
+// below the host's memory bandwidth, and a loop that waited for the copies would leave
+// the device idle meanwhile).  Not thread-safe: one host thread drives a server.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -20,6 +22,7 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -89,8 +92,8 @@ struct Arena {
   }
 };
 
-// Host copies split into pieces that the pool's threads and the calling thread take in
-// turn; copy() returns when every piece is done.
+// Host copies split into 1 MiB pieces that the pool's threads take in turn.  submit()
+// returns at once; a job's `done` runs on the thread that finishes its last piece.
 class CopyPool {
  public:
   struct Copy {
@@ -102,6 +105,7 @@ class CopyPool {
     for (int i = 0; i < threads; ++i) th_.emplace_back([this] { worker(); });
   }
   ~CopyPool() {
+    drain();
     {
       std::lock_guard<std::mutex> g(m_);
       stop_ = true;
@@ -109,83 +113,88 @@ class CopyPool {
     cv_.notify_all();
     for (auto& t : th_) t.join();
   }
-  void copy(const std::vector<Copy>& jobs) {
+  void submit(const std::vector<Copy>& jobs, std::function<void()> done) {
     static const size_t kPiece = 1u << 20;
-    auto w = std::make_shared<Work>();
-    size_t total = 0;
-    for (const Copy& c : jobs) {
-      total += c.n;
+    auto t = std::make_shared<Task>();
+    for (const Copy& c : jobs)
       for (size_t o = 0; o < c.n; o += kPiece)
-        w->p.push_back(Copy{(char*)c.dst + o, (const char*)c.src + o, std::min(kPiece, c.n - o)});
-    }
-    if (th_.empty() || total < 2 * kPiece) {
-      for (const Copy& c : jobs) memcpy(c.dst, c.src, c.n);
+        t->p.push_back(Copy{(char*)c.dst + o, (const char*)c.src + o, std::min(kPiece, c.n - o)});
+    if (t->p.empty() || th_.empty()) {  // nothing to copy, or no pool: on the caller
+      for (const Copy& c : t->p) memcpy(c.dst, c.src, c.n);
+      done();
       return;
     }
-    w->left = w->p.size();
+    t->left = t->p.size();
+    t->done = std::move(done);
     {
       std::lock_guard<std::mutex> g(m_);
-      cur_ = w;
-      ++gen_;
+      q_.push_back(t);
+      ++active_;
     }
     cv_.notify_all();
-    run(*w);
-    std::unique_lock<std::mutex> lk(w->m);
-    w->cv.wait(lk, [&] { return w->left.load() == 0; });
+  }
+  // Returns when every submitted job has completed (its `done` included).
+  void drain() {
+    std::unique_lock<std::mutex> lk(m_);
+    idle_.wait(lk, [&] { return active_ == 0; });
   }
 
  private:
-  struct Work {
+  struct Task {
     std::vector<Copy> p;
-    std::atomic<size_t> next{0}, left{0};
-    std::mutex m;
-    std::condition_variable cv;
+    size_t next = 0;  // next piece to hand out (under m_)
+    std::atomic<size_t> left{0};
+    std::function<void()> done;
   };
-  static void run(Work& w) {
-    for (;;) {
-      const size_t i = w.next.fetch_add(1);
-      if (i >= w.p.size()) return;
-      memcpy(w.p[i].dst, w.p[i].src, w.p[i].n);
-      if (w.left.fetch_sub(1) == 1) {
-        std::lock_guard<std::mutex> g(w.m);
-        w.cv.notify_all();
-      }
-    }
-  }
   void worker() {
-    uint64_t seen = 0;
     for (;;) {
-      std::shared_ptr<Work> w;
+      std::shared_ptr<Task> t;
+      size_t i = 0;
       {
         std::unique_lock<std::mutex> lk(m_);
-        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
-        if (stop_) return;
-        seen = gen_;
-        w = cur_;
+        cv_.wait(lk, [&] { return stop_ || !q_.empty(); });
+        if (q_.empty()) return;  // stop_ with nothing queued
+        t = q_.front();
+        i = t->next++;
+        if (t->next >= t->p.size()) q_.pop_front();
       }
-      run(*w);
+      memcpy(t->p[i].dst, t->p[i].src, t->p[i].n);
+      if (t->left.fetch_sub(1) == 1) {
+        t->done();
+        {
+          std::lock_guard<std::mutex> g(m_);
+          --active_;
+        }
+        idle_.notify_all();
+      }
     }
   }
   std::vector<std::thread> th_;
   std::mutex m_;
-  std::condition_variable cv_;
-  std::shared_ptr<Work> cur_;
-  uint64_t gen_ = 0;
+  std::condition_variable cv_, idle_;
+  std::deque<std::shared_ptr<Task>> q_;
+  size_t active_ = 0;  // jobs submitted and not yet completed
   bool stop_ = false;
 };
 
 struct Staging {
   void* host = nullptr;
   size_t cap = 0;
-  bool busy = false;
+  std::atomic<bool> busy{false};  // cleared by the copy thread that drains it
 };
+
+// A batch moves through: operands copied into its staging block (copy threads), then
+// upload, library call, download and event enqueued (the driving thread), then its
+// products copied out of staging (copy threads), then retired.
+enum BatchState { kCopyIn = 0, kReady, kLaunched, kCopyOut, kDone };
 
 struct Batch {
   std::vector<Req> reqs;
   std::vector<size_t> off_a, off_b, off_c;  // offsets inside the block (and staging)
   size_t op_bytes = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0, block = 0, block_bytes = 0;
-  int staging = -1;
+  Staging* stg = nullptr;  // its staging block (blocks never move: the copy threads use this)
   hipEvent_t ev = nullptr;
+  std::atomic<int> state{kCopyIn};
 };
 
 }  // namespace
@@ -198,15 +207,19 @@ struct ntt_server {
   std::vector<hipStream_t> streams;
   unsigned next_stream = 0;
   size_t max_batch = 64;
-  size_t staging_cap = 32u << 20;  // operand + product bytes of one polynomial batch (smaller batches: shorter tails)
-  std::vector<Staging> staging;
+  // operand + product bytes of one polynomial batch (smaller batches: shorter tails); a
+  // little over 32 MiB so that the largest single request of 2^20-word 64-bit operands
+  // (8 + 8 + 16 MiB, plus alignment) fits without a block of its own
+  size_t staging_cap = (32u << 20) + (1u << 16);
+  std::deque<Staging> staging;  // a deque: growing it moves no block the copy threads use
   std::vector<hipEvent_t> free_events;
   std::deque<Req> pending;
-  std::deque<Batch> inflight;
+  std::deque<std::shared_ptr<Batch>> inflight;  // admission order
   size_t max_inflight = 0;
   size_t inflight_cap = 8;  // batches in flight at once: 2 per stream, one staging block each
   CopyPool* pool = nullptr;
-  std::deque<uint64_t> finished;  // completed requests not yet handed back by progress()
+  std::mutex fin_m;
+  std::deque<uint64_t> finished;  // completed requests not yet handed back (under fin_m)
 };
 
 namespace {
@@ -223,20 +236,22 @@ bool page_locked(const void* ptr) {
   return e == hipSuccess && at.type == hipMemoryTypeHost;
 }
 
-int acquire_staging(ntt_server* s, size_t bytes, int* idx) {
-  for (size_t i = 0; i < s->staging.size(); ++i) {
-    if (!s->staging[i].busy && s->staging[i].cap >= bytes) {
-      s->staging[i].busy = true;
-      *idx = (int)i;
+int acquire_staging(ntt_server* s, size_t bytes, Staging** out) {
+  for (Staging& st : s->staging) {
+    if (!st.busy.load() && st.cap >= bytes) {
+      st.busy = true;
+      *out = &st;
       return NTT_OK;
     }
   }
-  Staging st;
-  st.cap = std::max(bytes, s->staging_cap);
-  if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess) return NTT_ENOMEM;
-  st.busy = true;
-  s->staging.push_back(st);
-  *idx = (int)s->staging.size() - 1;
+  const size_t cap = std::max(bytes, s->staging_cap);
+  void* host = nullptr;
+  if (hipHostMalloc(&host, cap, hipHostMallocDefault) != hipSuccess) return NTT_ENOMEM;
+  s->staging.emplace_back();
+  s->staging.back().host = host;
+  s->staging.back().cap = cap;
+  s->staging.back().busy = true;
+  *out = &s->staging.back();
   return NTT_OK;
 }
 
@@ -275,17 +290,27 @@ int layout(Batch& bt) {
   return NTT_OK;
 }
 
-int launch(ntt_server* s, Batch& bt) {
-  int rc = acquire_staging(s, bt.op_bytes + bt.out_bytes, &bt.staging);
+// Operands into the batch's staging block, on the copy threads; the batch turns kReady.
+int stage_in(ntt_server* s, const std::shared_ptr<Batch>& b) {
+  Batch& bt = *b;
+  int rc = acquire_staging(s, bt.op_bytes + bt.out_bytes, &bt.stg);
   if (rc) return rc;
-  unsigned char* host = (unsigned char*)s->staging[bt.staging].host;
+  unsigned char* host = (unsigned char*)bt.stg->host;
   std::vector<CopyPool::Copy> cp;
   for (size_t i = 0; i < bt.reqs.size(); ++i) {
     const Req& r = bt.reqs[i];
     cp.push_back(CopyPool::Copy{host + bt.off_a[i], r.a, r.la * r.esz()});
     cp.push_back(CopyPool::Copy{host + bt.off_b[i], r.b, r.lb * r.esz()});
   }
-  s->pool->copy(cp);
+  bt.state = kCopyIn;
+  s->pool->submit(cp, [b] { b->state = kReady; });
+  return NTT_OK;
+}
+
+// Upload, library call, download and event of a batch whose operands are staged.
+int enqueue(ntt_server* s, Batch& bt) {
+  int rc = NTT_OK;
+  unsigned char* host = (unsigned char*)bt.stg->host;
   hipStream_t st = s->streams[s->next_stream++ % s->streams.size()];
   unsigned char* dev = s->dbuf + bt.block;
   if (hipMemcpyAsync(dev, host, bt.op_bytes, hipMemcpyHostToDevice, st) != hipSuccess) return NTT_EDEVICE;
@@ -318,14 +343,38 @@ int launch(ntt_server* s, Batch& bt) {
   if (staged && hipMemcpyAsync(host + bt.op_bytes, dev + bt.op_bytes, bt.out_bytes, hipMemcpyDeviceToHost, st) !=
                     hipSuccess)
     return NTT_EDEVICE;
-  if (!s->free_events.empty()) {
-    bt.ev = s->free_events.back();
-    s->free_events.pop_back();
-  } else if (hipEventCreateWithFlags(&bt.ev, hipEventDisableTiming) != hipSuccess) {
-    return NTT_EDEVICE;
+  if (!bt.ev) {
+    if (!s->free_events.empty()) {
+      bt.ev = s->free_events.back();
+      s->free_events.pop_back();
+    } else if (hipEventCreateWithFlags(&bt.ev, hipEventDisableTiming) != hipSuccess) {
+      return NTT_EDEVICE;
+    }
   }
   if (hipEventRecord(bt.ev, st) != hipSuccess) return NTT_EDEVICE;
   return NTT_OK;
+}
+
+// Products of a batch finished on the device out of staging into the requests'
+// buffers, on the copy threads; then the ids queue for hand-back and the staging block
+// is free again.
+void stage_out(ntt_server* s, const std::shared_ptr<Batch>& b) {
+  const Batch& bt = *b;
+  const unsigned char* host = (const unsigned char*)bt.stg->host;
+  std::vector<CopyPool::Copy> cp;
+  for (size_t i = 0; i < bt.reqs.size(); ++i) {
+    const Req& r = bt.reqs[i];
+    if (r.c && !r.direct) cp.push_back(CopyPool::Copy{r.c, host + bt.off_c[i], r.out_elems() * r.out_esz()});
+  }
+  b->state = kCopyOut;
+  s->pool->submit(cp, [s, b] {
+    {
+      std::lock_guard<std::mutex> g(s->fin_m);
+      for (const Req& r : b->reqs) s->finished.push_back(r.id);
+    }
+    b->stg->busy = false;
+    b->state = kDone;
+  });
 }
 
 }  // namespace
@@ -364,16 +413,21 @@ int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t m
     }
     s->streams.push_back(st);
   }
-  // page-locked staging allocated once (its allocation is slow), one block per batch in flight
-  s->inflight_cap = 2 * (size_t)streams;
+  // page-locked staging allocated once (its allocation is slow), one block per batch in
+  // flight (a batch holds its block from the operands' copy until its products are out);
+  // batches in flight per stream: the tuning choice server.batches_per_stream, else 2
+  int64_t per_stream = 2;
+  if (ntt_tune_get("server.batches_per_stream", &per_stream) != NTT_OK) per_stream = 2;
+  s->inflight_cap = (size_t)per_stream * (size_t)streams;
   for (size_t i = 0; i < s->inflight_cap; ++i) {
-    Staging st;
-    st.cap = s->staging_cap;
-    if (hipHostMalloc(&st.host, st.cap, hipHostMallocDefault) != hipSuccess) {
+    void* host = nullptr;
+    if (hipHostMalloc(&host, s->staging_cap, hipHostMallocDefault) != hipSuccess) {
       ntt_server_destroy(s);
       return NTT_ENOMEM;
     }
-    s->staging.push_back(st);
+    s->staging.emplace_back();
+    s->staging.back().host = host;
+    s->staging.back().cap = s->staging_cap;
   }
   *out = s;
   return NTT_OK;
@@ -382,8 +436,9 @@ int ntt_server_create(ntt_server** out, size_t hbm_budget, int streams, size_t m
 int ntt_server_destroy(ntt_server* s) {
   if (!s) return NTT_OK;
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-  for (Batch& b : s->inflight)
-    if (b.ev) (void)hipEventDestroy(b.ev);
+  if (s->pool) s->pool->drain();  // no copy may touch staging or requests after this
+  for (auto& b : s->inflight)
+    if (b->ev) (void)hipEventDestroy(b->ev);
   for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   for (Staging& st : s->staging)
@@ -415,34 +470,62 @@ int ntt_server_submit(ntt_server* s, uint64_t id, int kind, uint64_t p, const vo
   return NTT_OK;
 }
 
+namespace {
+
+// A batch that could not be enqueued: nothing of it is pending on the device once the
+// streams are drained; its memory goes back and its requests to the front of the queue.
+void give_back(ntt_server* s, const std::shared_ptr<Batch>& b) {
+  for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+  if (b->stg) b->stg->busy = false;
+  if (b->ev) s->free_events.push_back(b->ev);
+  b->ev = nullptr;
+  s->arena->release(b->block, b->block_bytes);
+  for (size_t i = b->reqs.size(); i-- > 0;) s->pending.push_front(b->reqs[i]);
+  for (auto it = s->inflight.begin(); it != s->inflight.end(); ++it)
+    if (*it == b) {
+      s->inflight.erase(it);
+      break;
+    }
+}
+
+}  // namespace
+
 int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* ndone) {
   if (!s || !ndone || (cap && !done_ids)) return NTT_EINVAL;
   *ndone = 0;
-  // completions, in launch order per stream; a finished batch frees its memory and its
-  // requests queue for hand-back (at most cap per call, the rest on later calls)
-  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
-    const hipError_t q = hipEventQuery(it->ev);
-    if (q == hipErrorNotReady) {
-      ++it;
-      continue;
+  // (1) device side: batches whose operands are staged are enqueued; batches whose work
+  // has finished give their memory back to the arena and start their copy-out
+  for (size_t k = 0; k < s->inflight.size(); ++k) {
+    std::shared_ptr<Batch> b = s->inflight[k];
+    const int st = b->state.load();
+    if (st == kReady) {
+      const int rc = enqueue(s, *b);
+      if (rc) {
+        give_back(s, b);
+        return rc;
+      }
+      b->state = kLaunched;
+    } else if (st == kLaunched) {
+      const hipError_t q = hipEventQuery(b->ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return NTT_EDEVICE;
+      s->arena->release(b->block, b->block_bytes);
+      stage_out(s, b);
     }
-    if (q != hipSuccess) return NTT_EDEVICE;
-    const unsigned char* host = (const unsigned char*)s->staging[it->staging].host;
-    std::vector<CopyPool::Copy> cp;
-    for (size_t i = 0; i < it->reqs.size(); ++i) {
-      const Req& r = it->reqs[i];
-      if (r.c && !r.direct) cp.push_back(CopyPool::Copy{r.c, host + it->off_c[i], r.out_elems() * r.out_esz()});
-      s->finished.push_back(r.id);
-    }
-    s->pool->copy(cp);
-    s->staging[it->staging].busy = false;
-    s->arena->release(it->block, it->block_bytes);
-    s->free_events.push_back(it->ev);
-    it = s->inflight.erase(it);
   }
-  // admissions in arrival order
+  // (2) retire batches whose products are out (their ids are already queued)
+  for (auto it = s->inflight.begin(); it != s->inflight.end();) {
+    if ((*it)->state.load() == kDone) {
+      s->free_events.push_back((*it)->ev);
+      it = s->inflight.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  // (3) admissions in arrival order: operands start their copy into staging
   while (!s->pending.empty() && s->inflight.size() < s->inflight_cap) {
-    Batch bt;
+    auto b = std::make_shared<Batch>();
+    Batch& bt = *b;
     if (s->pending.front().kind == 1) {
       bt.reqs.push_back(s->pending.front());
     } else {
@@ -467,23 +550,20 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
     }
     if (!placed) break;  // wait for memory to free up
     for (size_t i = 0; i < bt.reqs.size(); ++i) s->pending.pop_front();
-    int rc = launch(s, bt);
+    s->inflight.push_back(b);
+    const int rc = stage_in(s, b);
     if (rc) {
-      // nothing of the batch is pending on the device after a failed enqueue is drained:
-      // give its memory back and return its requests to the front of the queue
-      for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-      if (bt.staging >= 0) s->staging[bt.staging].busy = false;
-      if (bt.ev) s->free_events.push_back(bt.ev);
-      s->arena->release(bt.block, bt.block_bytes);
-      for (size_t i = bt.reqs.size(); i-- > 0;) s->pending.push_front(bt.reqs[i]);
+      give_back(s, b);
       return rc;
     }
-    s->inflight.push_back(bt);
     s->max_inflight = std::max(s->max_inflight, s->inflight.size());
   }
-  while (*ndone < cap && !s->finished.empty()) {
-    done_ids[(*ndone)++] = s->finished.front();
-    s->finished.pop_front();
+  {
+    std::lock_guard<std::mutex> g(s->fin_m);
+    while (*ndone < cap && !s->finished.empty()) {
+      done_ids[(*ndone)++] = s->finished.front();
+      s->finished.pop_front();
+    }
   }
   return NTT_OK;
 }
@@ -491,7 +571,14 @@ int ntt_server_progress(ntt_server* s, uint64_t* done_ids, size_t cap, size_t* n
 int ntt_server_stats(const ntt_server* s, size_t* pending, size_t* inflight, size_t* arena_used, size_t* max_inflight) {
   if (!s) return NTT_EINVAL;
   if (pending) *pending = s->pending.size();
-  if (inflight) *inflight = s->inflight.size() + s->finished.size();
+  if (inflight) {
+    // batches not yet retired whose products are still on the way, plus completed
+    // requests not yet handed back
+    size_t live = 0;
+    for (const auto& b : s->inflight) live += b->state.load() != kDone;
+    std::lock_guard<std::mutex> g(const_cast<ntt_server*>(s)->fin_m);
+    *inflight = live + s->finished.size();
+  }
   if (arena_used) *arena_used = s->arena->used;
   if (max_inflight) *max_inflight = s->max_inflight;
   return NTT_OK;

@@ -342,12 +342,17 @@ class NativeServer:
             dt = np.uint32 if (r.kind == "int" or r.p < (1 << 31)) else np.uint64
             # result buffers touched before the run, so that no page is first touched
             # by the copy-back inside it
-            r.result = None
+            # (a result array the request already carries, of the right size and type,
+            # is reused: callers that serve the same requests again keep their buffers)
+            reuse = (self.keep_results and not self.pinned_results and isinstance(r.result, np.ndarray)
+                     and r.result.size == n and r.result.dtype == dt)
+            if not reuse:
+                r.result = None
             if self.keep_results and self.pinned_results:
                 tdt = self.torch.int32 if dt == np.uint32 else self.torch.int64
                 r._pinned = self.torch.empty(n, dtype=tdt, pin_memory=True)
                 r.result = r._pinned.numpy().view(dt)
-            elif self.keep_results:
+            elif self.keep_results and not reuse:
                 r.result = np.zeros(n, dtype=dt)
                 r.result.fill(1)
             r.a = np.ascontiguousarray(r.a)

@@ -182,3 +182,31 @@ def test_native_server_pinned_results():
     for r in ints:
         assert_equal_u(r.result, oracle.intmul_pyint(r.a, r.b), "pinned integer request %d vs Python int" % r.rid)
     srv.close()
+
+
+def test_native_server_serves_again_into_the_same_buffers():
+    """A second run of the same requests writes into the host buffers of the first (the
+    caller's buffers, reused), with the products the requests have alone; with no copy
+    threads the staging copies run on the driving thread."""
+    torch_cuda()
+    reqs = _requests(40, rate=1e6, lo=8.0, hi=16.0, seed=12)
+    for threads in (7, 0):
+        ntt.tune_set("server.copy_threads", threads)
+        try:
+            srv = serve.NativeServer(budget_bytes=256 << 20, streams=4, max_batch=16)
+            srv.run(reqs, realtime=False)
+            srv.close()
+            bufs = [r.result for r in reqs]
+            for b in bufs:
+                b.fill(7)
+            say("native server again into the same buffers, %d copy threads" % threads)
+            srv = serve.NativeServer(budget_bytes=256 << 20, streams=4, max_batch=16)
+            srv.run(reqs, realtime=False)
+            st = srv.stats()
+            srv.close()
+        finally:
+            ntt.tune_set("server.copy_threads", 7)
+        assert st["pending"] == 0 and st["inflight"] == 0 and st["arena_used"] == 0
+        for r, b in zip(reqs, bufs):
+            assert r.result is b
+            assert_equal_u(r.result, _alone(r), "request %d served again (%d copy threads)" % (r.rid, threads))
