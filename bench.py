@@ -141,6 +141,8 @@ def main() -> int:
                     help="batch (default, the headline line) or one of the other configurations")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--matrix-n", type=int, default=0, help="polymatrix, intmatrix: one matrix size only (default 1 .. 32)")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="a tuning choice of the library (ntt_tune_set) applied before the run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -153,6 +155,9 @@ def main() -> int:
     from paper_1407_3383_amd import inputs, ntt
 
     torch.cuda.set_device(0)
+    for kv in args.tune:
+        key, val = kv.split("=", 1)
+        ntt.tune_set(key, int(val))
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib << 18  # int32 words
         src = torch.ones(n, dtype=torch.int32, device="cuda")
@@ -228,6 +233,7 @@ def main() -> int:
             "workload": "batched polymul: %d products mod %d, operands of length %d, transform length %d, one fused launch"
                         % (items, P, L, N),
             "items": items, "operand_len": L, "ntt_len": N, "p": P,
+            **({"tuning": dict(kv.split("=", 1) for kv in args.tune)} if args.tune else {}),
         },
         "hbm": {
             "algorithmic_bytes_per_step": alg_bytes,
@@ -237,7 +243,8 @@ def main() -> int:
         },
     }
     achieved_g = bfly_per_step / (kern_ms * 1e-3) / 1e9
-    traffic, why = measured_traffic() if (items, args.log2len) == (1024, 15) else (None, "not the profiled workload")
+    traffic, why = (measured_traffic() if (items, args.log2len) == (1024, 15) and not args.tune
+                    else (None, "not the profiled workload"))
     out["roofline"] = {
         "bound": "alu",
         "kernel": "polymul_fused_kernel<u32, 1024 threads, 2^14-word sub-problems>",

@@ -240,6 +240,9 @@ int polymul_batch_destroy(ntt_batch* batch);
  *                     14, 15 or 16 (default 16); above it the two-pass path (batches
  *                     keep the fused kernel up to 2^16)
  *   "fused.single.max.w64"  the same for 64-bit primes: 13, 14 or 15 (default 15)
+ *   "fused.m15.w32"  1: fused products of transform length 2^16 over 32-bit primes
+ *                     run as two sub-problems of 2^15 points (one operand's
+ *                     transform held in registers); 0 (default): four of 2^14
  *   "single.split.w32.L<L>" (11 <= L <= 16), "single.split.w64.L<L>" (11 <= L <= 15)
  *                     a single product of length 2^L runs its 2^d sub-problems of
  *                     2^(L-d) points on 2^d workgroups at once, then recombines them

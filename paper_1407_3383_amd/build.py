@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libntt_mi355x.so")
-SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_poly_w32.hip", "kernels_poly_w32c3.hip", "kernels_poly_w64.hip", "kernels_poly_f64.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip",
+SOURCES = ["host.cpp", "server.cpp", "kernels_poly.hip", "kernels_poly_w32.hip", "kernels_poly_w32c3.hip", "kernels_poly_w32c4.hip", "kernels_poly_w64.hip", "kernels_poly_f64.hip", "kernels_ntt.hip", "kernels_pass.hip", "kernels_split.hip", "kernels_crt.hip",
            "kernels_matrix.hip", "kernels_arith.hip", "kernels_tft.hip"]
 # Issue-rate probes of the vector ALU (measurement only, a library of their own).
 PROBE_SRC = "valu_rates.hip"

@@ -83,6 +83,7 @@ bool tune_valid(const std::string& key, int64_t v) {
   }
   if (sscanf(key.c_str(), "tft.rows.w%d%c", &w, &tail) == 1) return (w == 32 || w == 64) && (v == 0 || v == 1);
   if (key == "server.copy_threads") return v >= 0 && v <= 63;
+  if (key == "fused.m15.w32") return v == 0 || v == 1;
   if (key == "server.batches_per_stream") return v >= 1 && v <= 8;
   if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
     if (w == 32) return v >= 14 && v <= 16;
@@ -1122,6 +1123,14 @@ struct ProductShape {
 // Largest log2 N for which a single product (polymul_modp, each prime of intmul_crt)
 // takes the fused one-workgroup kernel; above it the two-pass path.  Batches always
 // take the fused kernel up to its limit.
+// Size class of a fused product (fused_class), except that with the tuning choice
+// fused.m15.w32 = 1 32-bit transforms of 2^16 take class 4: two sub-problems of 2^15
+// points instead of four of 2^14.
+int fclass(int wb, int L) {
+  if (wb == 32 && L == 16 && tune_value("fused.m15.w32", 0) != 0) return 4;
+  return fused_class(wb, L);
+}
+
 int fused_limit(int wb) { return (int)tune_value(tune_key("fused.single.max", wb, -1), fused_max_log2n(wb)); }
 
 // Path of a single product: the split latency path when a split depth is chosen for
@@ -1164,7 +1173,7 @@ size_t fused_launch_ws(int wb, int cls, size_t count, int cus) {
 
 size_t single_product_ws(const ProductShape& s, int cus) {
   if (s.split) return align256(((size_t)1 << s.L) * (s.wb / 8));  // the 2^split partials
-  return s.fused ? fused_launch_ws(s.wb, fused_class(s.wb, s.L), 1, cus) : multipass_product_ws(s);
+  return s.fused ? fused_launch_ws(s.wb, fclass(s.wb, s.L), 1, cus) : multipass_product_ws(s);
 }
 
 // Two-pass product of one pair (section 5.2 with Algorithm 1): column passes of
@@ -1317,19 +1326,19 @@ FusedItem fused_item(const ntt_plan* pl, const void* a, size_t la, const void* b
 // Scratch of a batch beyond its descriptor array: the largest park area of its
 // fused launches, or the largest two-pass product (they run one after the other).
 size_t batch_scratch(const std::vector<ProductShape>& shapes, int cus, size_t* nfused_out) {
-  size_t per_class[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  size_t per_class[2][kFusedClasses] = {};
   size_t nfused = 0, need = 0;
   for (const ProductShape& s : shapes) {
     if (s.L < 0) continue;
     if (s.fused) {
       ++nfused;
-      ++per_class[s.wb == 64][fused_class(s.wb, s.L)];
+      ++per_class[s.wb == 64][fclass(s.wb, s.L)];
     } else {
       need = std::max(need, multipass_product_ws(s));
     }
   }
   for (int w = 0; w < 2; ++w)
-    for (int c = 0; c < 4; ++c) need = std::max(need, fused_launch_ws(w ? 64 : 32, c, per_class[w][c], cus));
+    for (int c = 0; c < kFusedClasses; ++c) need = std::max(need, fused_launch_ws(w ? 64 : 32, c, per_class[w][c], cus));
   if (nfused_out) *nfused_out = nfused;
   return need;
 }
@@ -1380,7 +1389,7 @@ int polymul_modp_run(uint64_t p, const void* a, size_t la, const void* b, size_t
       fb.park = workspace;
       fb.count = 1;
       fb.single = fused_item(pl, a, la, b, lb, c);
-      HIP_TRY(launch_fused(s.wb, fused_class(s.wb, s.L), fb, 1, stream));
+      HIP_TRY(launch_fused(s.wb, fclass(s.wb, s.L), fb, 1, stream));
       return ok();
     }
     rc = run_multipass_product(pl, a, la, b, lb, c, s.lc, false, workspace, stream);
@@ -1459,11 +1468,11 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
     struct Group { int wb, cls; size_t first, count; };
     std::vector<Group> groups;
     for (int wb : {32, 64}) {
-      for (int cls = 0; cls < 4; ++cls) {
+      for (int cls = 0; cls < kFusedClasses; ++cls) {
         const size_t first = items.size();
         for (size_t i = 0; i < count; ++i) {
           const ProductShape& s = shapes[i];
-          if (s.L < 0 || !s.fused || s.wb != wb || fused_class(wb, s.L) != cls) continue;
+          if (s.L < 0 || !s.fused || s.wb != wb || fclass(wb, s.L) != cls) continue;
           ntt_plan* pl = nullptr;
           int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
           if (rc) return rc;
@@ -1549,11 +1558,11 @@ int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t coun
     bt->big_ws = 0;
     std::vector<FusedItem> items;
     for (int wb : {32, 64}) {
-      for (int cls = 0; cls < 4; ++cls) {
+      for (int cls = 0; cls < kFusedClasses; ++cls) {
         const size_t first = items.size();
         for (size_t i = 0; i < count; ++i) {
           const ProductShape& s = shapes[i];
-          if (s.L < 0 || !s.fused || s.wb != wb || fused_class(wb, s.L) != cls) continue;
+          if (s.L < 0 || !s.fused || s.wb != wb || fclass(wb, s.L) != cls) continue;
           ntt_plan* pl = nullptr;
           int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
           if (rc) {
@@ -1801,7 +1810,7 @@ IntLayout int_layout(size_t na, size_t nb) {
     z.o_b32 = off;
     off += align256(nb * 4);
     z.o_big = off;  // park area of the fused launches
-    off += fused_launch_ws(32, fused_class(32, z.L), 1, current_cus());
+    off += fused_launch_ws(32, fclass(32, z.L), 1, current_cus());
   } else {
     z.o_big = off;
     off += 3 * 2 * align256(z.N * 4);  // the three primes' products share their launches
@@ -1862,7 +1871,7 @@ int intmul_crt(const uint16_t* a, size_t na, const uint16_t* b, size_t nb, uint3
         fb.count = 1;
         fb.park = w + z.o_big;
         fb.single = fused_item(pls[i], a_in, na, b_in, nb, r[i]);
-        HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
+        HIP_TRY(launch_fused(32, fclass(32, z.L), fb, 1, stream));
       }
     } else {
       void* outs[3] = {r[0], r[1], r[2]};
@@ -1955,7 +1964,7 @@ Int32Layout int32_layout(size_t na, size_t nb) {
   z.o_b = off;
   off += align256(nb * 4);
   z.o_big = off;
-  off += z.fused ? fused_launch_ws(32, fused_class(32, z.L), 1, current_cus()) : 3 * 2 * align256(z.N * 4);
+  off += z.fused ? fused_launch_ws(32, fclass(32, z.L), 1, current_cus()) : 3 * 2 * align256(z.N * 4);
   z.total = off;
   return z;
 }
@@ -2031,7 +2040,7 @@ int intmul_crt32(const uint32_t* a, size_t na, const uint32_t* b, size_t nb, uin
         fb.count = 1;
         fb.park = w + z.o_big;
         fb.single = fused_item(pls[i], ar, na, br, nb, r[i]);
-        HIP_TRY(launch_fused(32, fused_class(32, z.L), fb, 1, stream));
+        HIP_TRY(launch_fused(32, fclass(32, z.L), fb, 1, stream));
       }
     } else {
       // the column pass reduces the chunks as it loads them (input kind 2)
@@ -2392,11 +2401,11 @@ int polymul_f64_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t 
     bt->ditems = nullptr;
     std::vector<FusedItem> items;
     for (int band = 0; band < 2; ++band) {
-      for (int cls = 0; cls < 4; ++cls) {
+      for (int cls = 0; cls < kFusedClasses; ++cls) {
         const size_t first = items.size();
         for (size_t i = 0; i < count; ++i) {
           const ProductShape& s = shapes[i];
-          if (s.L < 0 || !s.fused || fused_class(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
+          if (s.L < 0 || !s.fused || fclass(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
           ntt_plan* pl = nullptr;
           int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
           if (rc) {
@@ -2485,11 +2494,11 @@ int polymul_f64_batch(const ntt_polymul_desc* d, size_t count, void* workspace, 
     struct Group { int cls; bool band; size_t first, count; };
     std::vector<Group> groups;
     for (int band = 0; band < 2; ++band) {
-      for (int cls = 0; cls < 4; ++cls) {
+      for (int cls = 0; cls < kFusedClasses; ++cls) {
         const size_t first = items.size();
         for (size_t i = 0; i < count; ++i) {
           const ProductShape& s = shapes[i];
-          if (s.L < 0 || !s.fused || fused_class(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
+          if (s.L < 0 || !s.fused || fclass(64, s.L) != cls || f64_band(s.p) != (band != 0)) continue;
           ntt_plan* pl = nullptr;
           int rc = cached_plan(s.p, (uint32_t)s.L, &pl, true);
           if (rc) return rc;

@@ -21,6 +21,7 @@ struct FusedBatch {
 };
 
 int fused_class(int word_bits, int log2n);
+constexpr int kFusedClasses = 5;  // class 4: 32-bit transforms of 2^16 as two 2^15-point sub-problems
 int fused_max_log2n(int word_bits);
 size_t fused_park_words(int word_bits, int cls);
 int fused_grid(int word_bits, int cls, size_t count, int cus);

@@ -298,9 +298,9 @@ __device__ void row_polymul_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid
     T x = sa[lidx(j)], y = sb[lidx(j)];
     if constexpr (LAZY == kLazy) {
       x = ar.red1(ar.red2(x));
-    } else {
+    } else {  // x < p, y < 2p: x y < 2p^2 < 2^bits p (Function 13's bound)
       x = ar.red1(x);
-      y = ar.red1(y);
+      if constexpr (LAZY == kBand) y = ar.red1(y);  // Function 16 needs x y < 2^50 p
     }
     T z = ar.mont(x, y);
     if constexpr (LAZY != kLazy) z = ar.red1(z);

@@ -352,9 +352,9 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
           T xa = x[0][i], yb = x[1][i];
           if constexpr (LAZY == kLazy) {
             xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
-          } else {
+          } else {  // xa < p, yb < 2p: xa yb < 2p^2 < 2^bits p (Function 13's bound)
             xa = ar.red1(xa);
-            yb = ar.red1(yb);
+            if constexpr (LAZY == kBand) yb = ar.red1(yb);  // Function 16 needs xa yb < 2^50 p
           }
           T z = ar.mont(xa, yb);  // (0, 2p); the Montgomery scale was applied to b
           if constexpr (LAZY != kLazy) z = ar.red1(z);

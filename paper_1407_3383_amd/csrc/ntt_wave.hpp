@@ -1,4 +1,4 @@
-// Wave-local transform of LDS-resident vectors of 2^M words, 10 <= M <= 14.
+// Wave-local transform of LDS-resident vectors of 2^M words, 10 <= M <= 15.
 //
 // The M index bits are split into a workgroup part G (bits M-1 .. 10, radix
 // 2^(M-10) clusters at stride 1024, one barrier-separated round) and three
@@ -108,14 +108,15 @@ __device__ __forceinline__ void fwd_G(const Arith<T>& ar, T* const (&sv)[NV], in
   }
 }
 
-// Rounds W1..W3 of block B = wave id; the result stays in x[v][16] with
+// Rounds W1..W3 of block B = wave id (or of block `blk` when it is given: a wave
+// may own several blocks); the result stays in x[v][16] with
 // x[v][4 k + c] = element 1024 B + 4 (lane + 64 k) + c.
 template <typename T, int LAZY, int NV, int M>
 __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
-                                      gcptr<TwPair<T>> tw, T (&x)[NV][16]) {
+                                      gcptr<TwPair<T>> tw, T (&x)[NV][16], int blk = -1) {
   const int tid = opaque_tid();
   const int lane = tid & 63;
-  const uint32_t B = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t B = blk >= 0 ? (uint32_t)blk : (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
   const int base = (int)B << 10;
   const int lbase = base + ((int)B << 5);  // lidx(base)
   TwPair<T> w[15];
@@ -176,10 +177,10 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
 // Rounds W3'..W1' from registers (layout of fwd_W), result stored to LDS.
 template <typename T, int LAZY, int M>
 __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi,
-                                      T (&x)[16]) {
+                                      T (&x)[16], int blk = -1) {
   const int tid = opaque_tid();
   const int lane = tid & 63;
-  const uint32_t B = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t B = blk >= 0 ? (uint32_t)blk : (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
   const int base = (int)B << 10;
   const int lbase = base + ((int)B << 5);
   // W3': bits 1..0.

@@ -104,9 +104,9 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
           T xa = x[0][i], yb = x[1][i];
           if constexpr (LAZY == kLazy) {
             xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
-          } else {
+          } else {  // xa < p, yb < 2p: xa yb < 2p^2 < 2^bits p (Function 13's bound)
             xa = ar.red1(xa);
-            yb = ar.red1(yb);
+            if constexpr (LAZY == kBand) yb = ar.red1(yb);  // Function 16 needs xa yb < 2^50 p
           }
           T z = ar.mont(xa, yb);  // (0, 2p)
           if constexpr (LAZY != kLazy) z = ar.red1(z);
@@ -125,9 +125,9 @@ __device__ void polymul_item(const FusedItem& it, T* sa, T* sb, T* park_generic)
           T x = sa[lidx(j)], y = sb[lidx(j)];
           if constexpr (LAZY == kLazy) {
             x = ar.red1(ar.red2(x));  // x < p, y < 4p: x y < 2^bits p
-          } else {
+          } else {  // x < p, y < 2p: x y < 2p^2 < 2^bits p (Function 13's bound)
             x = ar.red1(x);
-            y = ar.red1(y);
+            if constexpr (LAZY == kBand) y = ar.red1(y);  // Function 16 needs x y < 2^50 p
           }
           T z = ar.mont(x, y);  // (0, 2p)
           if constexpr (LAZY != kLazy) z = ar.red1(z);
@@ -386,9 +386,9 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         T xa = x[0][i], yb = x[1][i];
         if constexpr (LAZY == kLazy) {
           xa = ar.red1(ar.red2(xa));  // xa < p, yb < 4p: xa yb < 2^bits p
-        } else {
+        } else {  // xa < p, yb < 2p: xa yb < 2p^2 < 2^bits p (Function 13's bound)
           xa = ar.red1(xa);
-          yb = ar.red1(yb);
+          if constexpr (LAZY == kBand) yb = ar.red1(yb);  // Function 16 needs xa yb < 2^50 p
         }
         T z = ar.mont(xa, yb);  // (0, 2p)
         if constexpr (LAZY != kLazy) z = ar.red1(z);
@@ -471,6 +471,186 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   }
 }
 
+// Products of transform length 2^16 over 32-bit words as two sub-problems of 2^15
+// points (d = 1) in one workgroup of 1024 threads.  LDS holds one operand's
+// sub-problem (2^15 words), so the first operand's transform stays in registers (two
+// 1024-word blocks per wave, 32 words per thread) while the second is transformed in
+// LDS; the entry-wise product and the inverse then run as in polymul_item_wave.
+// Against four sub-problems of 2^14 this reads each operand twice instead of four
+// times, parks one partial instead of three, and its fold is one addition (the
+// sub-problem inputs are a_lo + a_hi and a_lo - a_hi, or the operand itself when it
+// has at most 2^15 coefficients).  Per sub-problem h:
+//   A: fold of a, top 5 stages (radix-32 clusters at stride 1024), LDS;  barrier;
+//      wave-local rounds of the wave's two blocks, kept in registers;    barrier;
+//   B: the same for b (scaled by sigma);                                  barrier;
+//      wave-local rounds of b, entry-wise product, wave-local inverse;    barrier;
+//   G': top 5 inverse stages; park (h = 0) or recombine with the parked partial.
+// HI: an operand may have more than 2^15 coefficients (a fold of two halves).
+template <typename T, int LAZY, bool HI>
+__device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, T* park_generic) {
+  constexpr int M = 15, S = 1 << M, C = 32, d = 1;
+  FusedItem it;
+  it.a = uni(it_in.a);
+  it.b = uni(it_in.b);
+  it.c = uni(it_in.c);
+  it.la = uni((uint64_t)it_in.la);
+  it.lb = uni((uint64_t)it_in.lb);
+  it.cst = uni(it_in.cst);
+  it.tw = uni(it_in.tw);
+  it.twi = uni(it_in.twi);
+  const gptr<T> park = gmut<T>(uni((void*)park_generic));
+  const gcptr<PolyConst<T>> pc = gconst<PolyConst<T>>(it.cst);
+  Arith<T> ar;
+  ar.p = uni(pc->p);
+  ar.p2 = uni(pc->p2);
+  ar.pinv = uni(pc->pinv);
+  const gcptr<TwPair<T>> tw = gconst<TwPair<T>>(it.tw);
+  const gcptr<TwPair<T>> twi = gconst<TwPair<T>>(it.twi);
+  const gcptr<T> a = gconst<T>(it.a);
+  const gcptr<T> b = gconst<T>(it.b);
+  const gptr<T> c = gmut<T>(it.c);
+  const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(opaque_tid() >> 6);
+  // Montgomery scale of the entry-wise product (2^32 / N), applied to b's inputs
+  const TwPair<T> sig = uni(ldtw<T>(&pc->fb[0][0]));
+
+  // fold inputs of one operand, requested ahead: lo[c] = x[q + 1024 c] (the upper
+  // half, x[q + 1024 c + S], is read where it is added: HI items are rare, and holding
+  // both halves across a phase would spill)
+  T lo[C];
+  auto request = [&](gcptr<T> x, uint64_t len) {
+    const int q = opaque_tid();
+    if (len >= (uint64_t)S) {
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) lo[cc] = x[q + 1024 * cc];
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const uint32_t j = (uint32_t)(q + 1024 * cc);
+        lo[cc] = j < len ? x[j] : (T)0;
+      }
+    }
+  };
+  // fold (u = lo + hi or lo - hi), optional scale, top 5 forward stages, store to LDS
+  auto top_forward = [&](int h, gcptr<T> x, uint64_t len, bool scale) {
+    const int q = opaque_tid();
+    T v[C];
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) {
+      T u = lo[cc];
+      if constexpr (HI) {
+        const uint64_t j = (uint64_t)(q + 1024 * cc) + S;
+        const T hv = j < len ? x[j] : (T)0;
+        u = h == 0 ? ar.red1(u + hv) : ar.red1(u - hv + ar.p);
+      }
+      if (scale) u = ar.red1(ar.shoup_u(u, sig.w, sig.ws));
+      v[cc] = u;
+    }
+    // cluster stage u pairs (cc, cc + 2^(4-u)) with TW[2^(d+u) + (h << u) + vv], vv = cc >> (5-u)
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int half = 16 >> u;
+#pragma unroll
+      for (int vv = 0; vv < (1 << u); ++vv) {
+        const TwPair<T> ww = uni(ldtw<T>(tw + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv)));
+#pragma unroll
+        for (int c2 = 0; c2 < half; ++c2) {
+          const int cc = (vv << (5 - u)) + c2;
+          ct_bfly<LAZY, true>(ar, v[cc], v[cc + half], ww);
+        }
+      }
+    }
+    const int lb0 = lidx(q);
+#pragma unroll
+    for (int cc = 0; cc < C; ++cc) sa[lb0 + cc * 1056] = v[cc];
+  };
+
+  request(a, la);
+  for (int h = 0; h < 2; ++h) {
+    // ---- A: fold, top stages, wave-local rounds kept in registers
+    top_forward(h, a, la, false);
+    __syncthreads();
+    T xa[2][16];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      T* const sv1[1] = {sa};
+      T x[1][16];
+      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xa[k][i] = x[0][i];
+    }
+    __syncthreads();
+    // ---- B: fold, scale, top stages; wave-local rounds, entry-wise product, inverse
+    request(b, lb);
+    top_forward(h, b, lb, true);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      T* const sv1[1] = {sa};
+      T x[1][16];
+      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T xv = xa[k][i], yv = x[0][i];
+        if constexpr (LAZY == kLazy) {
+          xv = ar.red1(ar.red2(xv));  // xv < p, yv < 4p: xv yv < 2^bits p
+        } else {  // xv < p, yv < 2p: xv yv < 2p^2 < 2^bits p (Function 13's bound)
+          xv = ar.red1(xv);
+          if constexpr (LAZY == kBand) yv = ar.red1(yv);  // Function 16 needs xv yv < 2^50 p
+        }
+        T z = ar.mont(xv, yv);  // (0, 2p)
+        if constexpr (LAZY != kLazy) z = ar.red1(z);
+        x[0][i] = z;
+      }
+      inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0], wave + 16 * k);
+    }
+    __syncthreads();
+    // ---- G': top 5 inverse stages; the next sub-problem's a is requested first
+    if (h == 0) request(a, la);
+    {
+      const int q = opaque_tid();
+      const int lb0 = lidx(q);
+      T v[C];
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) v[cc] = sa[lb0 + cc * 1056];
+#pragma unroll
+      for (int u = 4; u >= 0; --u) {
+        const int half = 16 >> u;
+#pragma unroll
+        for (int vv = 0; vv < (1 << u); ++vv) {
+          const TwPair<T> ww = uni(ldtw<T>(twi + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv)));
+#pragma unroll
+          for (int c2 = 0; c2 < half; ++c2) {
+            const int cc = (vv << (5 - u)) + c2;
+            gs_bfly<LAZY, true>(ar, v[cc], v[cc + half], ww);
+          }
+        }
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) park[q + 1024 * cc] = v[cc];
+      } else {
+        // the last inverse stage across the two partials: (u0, u1) -> (u0 + u1, (u0 - u1) w)
+        const TwPair<T> w1 = uni(ldtw<T>(twi + 1));
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) {
+          const uint32_t j = (uint32_t)(q + 1024 * cc);
+          T u0 = park[j], u1 = v[cc];
+          gs_bfly<LAZY, true>(ar, u0, u1, w1);
+          if (lc >= (uint64_t)2 * S - 1) {  // every output but possibly the last one exists
+            c[j] = canon_from_inv<LAZY>(ar, u0);
+            if (j + S < (uint32_t)lc) c[j + S] = canon_from_inv<LAZY>(ar, u1);
+          } else {
+            if (j < lc) c[j] = canon_from_inv<LAZY>(ar, u0);
+            if ((uint64_t)j + S < lc) c[j + S] = canon_from_inv<LAZY>(ar, u1);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // The arithmetic mode of the item's prime: kLazy or kSafe read from its constants, or
 // kBand in the kernels instantiated for residues in doubles with 2^49 <= p < 2^50 (a
 // kernel of their own, so that the extra reductions do not weigh on the register
@@ -478,7 +658,17 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
 template <typename T, int NT, int M, int MAXD, int PM, bool BAND>
 __device__ __forceinline__ void polymul_dispatch_lazy(const FusedItem& it, T* sa, T* sb, T* park) {
   const PolyConst<T>* pc = (const PolyConst<T>*)it.cst;
-  if constexpr (BAND) {
+  if constexpr (M == 15) {  // 32-bit words, transform length 2^16 (d = 1), no band
+    static_assert(NT == 1024 && !BAND && sizeof(T) == 4, "2^15-point sub-problems: 32-bit words, 1024 threads");
+    const bool hi = uni((uint64_t)it.la) > (1u << 15) || uni((uint64_t)it.lb) > (1u << 15);
+    if (uni(gconst<PolyConst<T>>(uni(it.cst))->lazy)) {
+      if (hi) polymul_item_w15<T, kLazy, true>(it, sa, park);
+      else polymul_item_w15<T, kLazy, false>(it, sa, park);
+    } else {
+      if (hi) polymul_item_w15<T, kSafe, true>(it, sa, park);
+      else polymul_item_w15<T, kSafe, false>(it, sa, park);
+    }
+  } else if constexpr (BAND) {
     if constexpr (M >= 10 && PM == 1) polymul_item_wave<T, kBand, NT, M, MAXD>(it, sa, sb, park);
     else polymul_item<T, kBand, NT, M, MAXD, PM>(it, sa, sb, park);
   } else if constexpr (M >= 10 && PM == 1) {
@@ -515,8 +705,8 @@ template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM, bool BAND = 
 __global__ __launch_bounds__(NT) void polymul_fused_kernel(FusedBatch batch) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sa = (T*)smem_raw;
-  T* sb = sa + lds_words(1 << LOGS);
-  T* park = PM == 1 ? (T*)batch.park + (size_t)blockIdx.x * 3 * ((size_t)1 << LOGS) : nullptr;
+  T* sb = LOGS == 15 ? nullptr : sa + lds_words(1 << LOGS);
+  T* park = PM == 1 ? (T*)batch.park + (size_t)blockIdx.x * (LOGS == 15 ? 1 : 3) * ((size_t)1 << LOGS) : nullptr;
   for (int i = blockIdx.x; i < batch.count; i += gridDim.x) {
     const FusedItem it = batch.items ? batch.items[i] : batch.single;
     polymul_dispatch<T, NT, LOGS, LMIN, MAXD, PM, BAND>(it, sa, sb, park);
@@ -525,7 +715,8 @@ __global__ __launch_bounds__(NT) void polymul_fused_kernel(FusedBatch batch) {
 
 template <typename T, int NT, int LOGS, int LMIN, int MAXD, int PM, bool BAND = false>
 hipError_t launch_fused_cls(const FusedBatch& batch, int grid, hipStream_t stream) {
-  const size_t lds = 2 * (size_t)lds_words(1 << LOGS) * sizeof(T);
+  // two operands' sub-problems in LDS, one for 2^15-point sub-problems
+  const size_t lds = (LOGS == 15 ? 1 : 2) * (size_t)lds_words(1 << LOGS) * sizeof(T);
   auto k = polymul_fused_kernel<T, NT, LOGS, LMIN, MAXD, PM, BAND>;
   hipError_t e = allow_dynamic_lds((const void*)k, lds);
   if (e != hipSuccess) return e;
@@ -536,6 +727,7 @@ hipError_t launch_fused_cls(const FusedBatch& batch, int grid, hipStream_t strea
 // One translation unit per word type and class group (compiled in parallel).
 hipError_t launch_fused_w32_small(int cls, const FusedBatch& batch, int grid, hipStream_t stream);
 hipError_t launch_fused_w32_c3(const FusedBatch& batch, int grid, hipStream_t stream);
+hipError_t launch_fused_w32_c4(const FusedBatch& batch, int grid, hipStream_t stream);
 hipError_t launch_fused_w64(int cls, const FusedBatch& batch, int grid, hipStream_t stream);
 
 }  // namespace nttgpu
