@@ -19,7 +19,7 @@ namespace {
 
 enum {
   OP_ADD = 0, OP_SUB, OP_ADD3, OP_MIN, OP_MUL_LO, OP_MUL_HI, OP_MAD64, OP_CNDMASK, OP_FMA_F64, OP_XOR,
-  OP_LSHL_ADD, OP_CT31, OP_CT_LAZY, OP_GS31, OP_GS_LAZY, OP_COUNT
+  OP_LSHL_ADD, OP_CT31, OP_CT_LAZY, OP_GS31, OP_GS_LAZY, OP_DPP_MOV, OP_PERMLANE32_SWAP, OP_DS_BPERMUTE, OP_COUNT
 };
 
 template <int OP>
@@ -91,6 +91,44 @@ __global__ __launch_bounds__(256) void rate_fma64_kernel(uint32_t* out, int iter
   uint32_t r = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) r ^= (uint32_t)__double_as_longlong(x[k]);
+  out[tid] = r;
+}
+
+// Cross-lane moves, the alternatives to an exchange through LDS between the wave-local
+// rounds: a DPP row shift (v_mov_b32 with row_shr:1, a VALU instruction), gfx950's
+// v_permlane32_swap (swaps the upper half-wave of one register with the lower of
+// another: one instruction per register pair) and ds_bpermute (a lane gather through
+// the LDS crossbar, issued on the LDS pipe).  Built-ins, so that the compiler places the
+// wait states DPP needs.  8 chains per thread; per iteration 128 moves (64 swaps).
+template <int OP>
+__global__ __launch_bounds__(256) void rate_xlane_kernel(uint32_t* out, int iters) {
+  const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int addr = (int)(((threadIdx.x & 63u) ^ 1u) << 2);  // neighbouring lane
+  uint32_t x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = tid * 8u + (uint32_t)k;
+  for (int i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      if constexpr (OP == OP_DPP_MOV) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = __builtin_amdgcn_update_dpp(0u, x[k], 0x111, 0xf, 0xf, false);
+      } else if constexpr (OP == OP_PERMLANE32_SWAP) {
+#pragma unroll
+        for (int k = 0; k < 8; k += 2) {
+          const auto r = __builtin_amdgcn_permlane32_swap(x[k], x[k + 1], false, false);
+          x[k] = r[0];
+          x[k + 1] = r[1];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)x[k]);
+      }
+    }
+  }
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r ^= x[k];
   out[tid] = r;
 }
 
@@ -166,6 +204,9 @@ int valu_rate_launch(int op, int grid, int iters, void* out, uint64_t p, uint32_
     case OP_GS_LAZY:
       hipLaunchKernelGGL((rate_bfly_kernel<true, true>), g, b, 0, s, o, iters, (uint32_t)p, pinv, w, ws);
       break;
+    case OP_DPP_MOV: hipLaunchKernelGGL(rate_xlane_kernel<OP_DPP_MOV>, g, b, 0, s, o, iters); break;
+    case OP_PERMLANE32_SWAP: hipLaunchKernelGGL(rate_xlane_kernel<OP_PERMLANE32_SWAP>, g, b, 0, s, o, iters); break;
+    case OP_DS_BPERMUTE: hipLaunchKernelGGL(rate_xlane_kernel<OP_DS_BPERMUTE>, g, b, 0, s, o, iters); break;
     default: return (int)hipErrorInvalidValue;
   }
   return (int)hipGetLastError();

@@ -30,7 +30,10 @@ PROBES = [
     ("v_cndmask_b32", 7, "op"), ("v_fma_f64", 8, "op"), ("v_xor_b32", 9, "op"), ("v_lshl_add_u32", 10, "op"),
     ("CT butterfly, 31-bit p (2013265921)", 11, "bfly"), ("CT butterfly, lazy, p < 2^30 (998244353)", 12, "bfly"),
     ("GS butterfly, 31-bit p (2013265921)", 13, "bfly"), ("GS butterfly, lazy, p < 2^30 (998244353)", 14, "bfly"),
+    ("v_mov_b32 DPP row_shr:1", 15, "op"), ("v_permlane32_swap_b32 (one per register pair)", 16, "op"),
+    ("ds_bpermute_b32", 17, "op"),
 ]
+PER_ITER_OF = {16: 64}     # the swap probe issues 64 instructions per thread and iteration
 PER_ITER = 16 * 8          # operations (or butterflies) per thread and iteration
 CUS, LANES, CLOCK_HZ = 256, 64, 2.4e9
 UNIT_PEAK = CUS * LANES * CLOCK_HZ  # one 32-bit VALU lane-op per lane per clock: 39.3 T/s
@@ -76,7 +79,7 @@ def measure(iters: int = 2000, grid: int = 8192, reps: int = 5):
                 e1.synchronize()
                 ms = e0.elapsed_time(e1)
                 best = ms if best is None else min(best, ms)
-        count = grid * 256 * iters * PER_ITER
+        count = grid * 256 * iters * PER_ITER_OF.get(op, PER_ITER)
         rate = count / (best * 1e-3)
         rows.append({"probe": name, "kind": kind, "ms": best, "count": count, "rate": rate,
                      "per_cu_clock": rate / (CUS * CLOCK_HZ)})
