@@ -205,8 +205,12 @@ size_t polymul_batch_workspace_bytes(const ntt_polymul_desc* d, size_t count);
  * workgroup size and LDS), and each group is ONE persistent fused launch (fold,
  * forward x2, entry-wise product, inverse, combine) whatever the primes and
  * lengths of its products (section 2.2, Remark 6: several moduli in one vector
- * launch); the groups' launches run one after another on hip_stream, then the
- * larger products run the multi-pass path one after another.
+ * launch); the larger products run the multi-pass path one after another.  The
+ * groups' launches and the multi-pass sequence are independent: the first runs on
+ * hip_stream, the others on streams forked from it (an event) and joined back into it
+ * before the call returns, so that they overlap on the device; hip_stream orders
+ * everything the call enqueues, as if it had run there alone (while a graph is being
+ * captured, or with the tuning choice "batch.fork" = 0, everything runs on hip_stream).
  * `d` is a HOST array; its content is copied into the workspace.
  * Errors as polymul_modp, checked for every descriptor before anything runs. */
 int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace, size_t ws_bytes,
@@ -214,13 +218,18 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
 
 /* Reusable batch: the descriptors are checked, their plans created and their
  * device form uploaded once (synchronously) into device memory the handle owns;
- * every launch then only enqueues kernels on `hip_stream` (nothing is copied or
- * allocated), so a launch can be repeated, overlapped on several streams when the
- * operands differ, or captured in a HIP graph.  The operand pointers are bound at
- * creation.  Errors as polymul_modp_batch. */
+ * every launch then only enqueues kernels on `hip_stream` and on the streams its
+ * launches fork onto, joined back into `hip_stream` as in polymul_modp_batch (nothing
+ * is copied or allocated on the device; the first launch from a stream creates the
+ * streams it forks onto), so a launch can be repeated, overlapped on several streams
+ * when the operands differ, or captured in a HIP graph (captured launches stay on
+ * `hip_stream`).  The operand pointers are bound at creation.  Errors as
+ * polymul_modp_batch. */
 typedef struct ntt_batch ntt_batch;
 int polymul_batch_create(ntt_batch** out, const ntt_polymul_desc* d, size_t count);
-/* Device scratch needed by polymul_batch_launch (0 when every product is fused). */
+/* Device scratch needed by polymul_batch_launch: a park area for each launch of
+ * 2^14..2^16-point products (32-bit primes) and the largest multi-pass product's
+ * scratch; 0 when there is neither. */
 size_t polymul_batch_launch_workspace_bytes(const ntt_batch* batch);
 int polymul_batch_launch(const ntt_batch* batch, void* workspace, size_t ws_bytes, void* hip_stream);
 /* NULL is accepted; the caller makes sure no launch of the batch is still pending. */
@@ -240,6 +249,9 @@ int polymul_batch_destroy(ntt_batch* batch);
  *                     14, 15 or 16 (default 16); above it the two-pass path (batches
  *                     keep the fused kernel up to 2^16)
  *   "fused.single.max.w64"  the same for 64-bit primes: 13, 14 or 15 (default 15)
+ *   "batch.fork"     1 (default): a batch's size classes and multi-pass products run on
+ *                     forked streams (polymul_modp_batch, polymul_batch_launch); 0: all on
+ *                     the caller's stream
  *   "fused.m15.w32"  1: fused products of transform length 2^16 over 32-bit primes
  *                     run as two sub-problems of 2^15 points (one operand's
  *                     transform held in registers); 0 (default): four of 2^14

@@ -83,6 +83,7 @@ bool tune_valid(const std::string& key, int64_t v) {
   }
   if (sscanf(key.c_str(), "tft.rows.w%d%c", &w, &tail) == 1) return (w == 32 || w == 64) && (v == 0 || v == 1);
   if (key == "server.copy_threads") return v >= 0 && v <= 63;
+  if (key == "batch.fork") return v == 0 || v == 1;
   if (key == "fused.m15.w32") return v == 0 || v == 1;
   if (key == "server.batches_per_stream") return v >= 1 && v <= 8;
   if (sscanf(key.c_str(), "fused.single.max.w%d%c", &w, &tail) == 1) {
@@ -591,6 +592,7 @@ struct Staging {
 
 struct DeviceCtx {
   std::mutex mu;
+  std::map<hipStream_t, std::vector<hipStream_t>> lanes;  // fork streams per caller stream
   std::map<std::pair<uint64_t, uint32_t>, ntt_plan*> plans;
   Staging ring[8];
   unsigned next = 0;
@@ -1323,25 +1325,79 @@ FusedItem fused_item(const ntt_plan* pl, const void* a, size_t la, const void* b
   return it;
 }
 
-// Scratch of a batch beyond its descriptor array: the largest park area of its
-// fused launches, or the largest two-pass product (they run one after the other).
+// Scratch of a batch beyond its descriptor array: one park area per fused launch that
+// parks partials (the launches may run at once, on forked streams), then the largest
+// two-pass product (they run one after the other).
 size_t batch_scratch(const std::vector<ProductShape>& shapes, int cus, size_t* nfused_out) {
   size_t per_class[2][kFusedClasses] = {};
-  size_t nfused = 0, need = 0;
+  size_t nfused = 0, big = 0, parks = 0;
   for (const ProductShape& s : shapes) {
     if (s.L < 0) continue;
     if (s.fused) {
       ++nfused;
       ++per_class[s.wb == 64][fclass(s.wb, s.L)];
     } else {
-      need = std::max(need, multipass_product_ws(s));
+      big = std::max(big, multipass_product_ws(s));
     }
   }
   for (int w = 0; w < 2; ++w)
-    for (int c = 0; c < kFusedClasses; ++c) need = std::max(need, fused_launch_ws(w ? 64 : 32, c, per_class[w][c], cus));
+    for (int c = 0; c < kFusedClasses; ++c) parks += fused_launch_ws(w ? 64 : 32, c, per_class[w][c], cus);
   if (nfused_out) *nfused_out = nfused;
-  return need;
+  return parks + big;
 }
+
+// The independent launches of one batch call (one per size class, and the two-pass
+// products as one sequence): unit 0 runs on the caller's stream, unit k > 0 on a
+// stream forked from it (created once per caller stream, default priority) and joined
+// back into it, so that classes that fill few CUs and the two-pass products overlap.
+// Everything stays on the caller's stream while a graph is being captured, for a single
+// unit, or with the tuning choice batch.fork = 0.
+class Fork {
+ public:
+  Fork(hipStream_t s, int units) : main_(s), units_(units) {}
+  ~Fork() {
+    if (e0_) (void)hipEventDestroy(e0_);
+  }
+  int begin() {
+    if (units_ < 2 || capturing(main_) || tune_value("batch.fork", 1) == 0) return NTT_OK;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    DeviceCtx* ctx = device_ctx(dev);
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      std::vector<hipStream_t>& v = ctx->lanes[main_];
+      while ((int)v.size() < units_ - 1) {
+        hipStream_t t = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));  // default priority
+        v.push_back(t);
+      }
+      lanes_.assign(v.begin(), v.begin() + (units_ - 1));
+    }
+    HIP_TRY(hipEventCreateWithFlags(&e0_, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(e0_, main_));
+    for (hipStream_t l : lanes_) HIP_TRY(hipStreamWaitEvent(l, e0_, 0));
+    return NTT_OK;
+  }
+  hipStream_t lane(int k) const { return k == 0 || lanes_.empty() ? main_ : lanes_[k - 1]; }
+  int join() {
+    for (hipStream_t l : lanes_) {
+      hipEvent_t e = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      const hipError_t r1 = hipEventRecord(e, l);
+      const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(main_, e, 0) : r1;
+      (void)hipEventDestroy(e);
+      HIP_TRY(r2);
+    }
+    lanes_.clear();
+    return NTT_OK;
+  }
+
+ private:
+  hipStream_t main_;
+  int units_;
+  std::vector<hipStream_t> lanes_;
+  hipEvent_t e0_ = nullptr;
+};
 
 // polymul_modp's checks and launches; create_plans = false: a missing plan is an
 // error instead of being created (no device allocation).
@@ -1486,24 +1542,34 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
       int rc = upload(ctx, ditems, items.data(), items.size() * sizeof(FusedItem), stream);
       if (rc) return rc;
     }
-    void* bigws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
-    for (const Group& g : groups) {
+    unsigned char* ws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
+    const bool any_big = nfused < count && std::any_of(shapes.begin(), shapes.end(),
+                                                       [](const ProductShape& s) { return s.L >= 0 && !s.fused; });
+    Fork fork(stream, (int)groups.size() + (any_big ? 1 : 0));
+    int rc = fork.begin();
+    if (rc) return rc;
+    for (size_t k = 0; k < groups.size(); ++k) {
+      const Group& g = groups[k];
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = ditems + g.first;
-      fb.park = bigws;
+      fb.park = ws;  // this launch's own park area
       fb.count = (int)g.count;
-      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, cus), stream));
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, cus), fork.lane((int)k)));
+      ws += fused_launch_ws(g.wb, g.cls, g.count, cus);
     }
     for (size_t i = 0; i < count; ++i) {
       const ProductShape& s = shapes[i];
       if (s.L < 0 || s.fused) continue;
       ntt_plan* pl = nullptr;
-      int rc = cached_plan(s.p, (uint32_t)s.L, &pl);
+      rc = cached_plan(s.p, (uint32_t)s.L, &pl);
       if (rc) return rc;
-      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, bigws, stream);
+      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, ws,
+                                 fork.lane((int)groups.size()));
       if (rc) return rc;
     }
+    rc = fork.join();
+    if (rc) return rc;
     return ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in polymul_modp_batch");
@@ -1616,20 +1682,32 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
     if (dev != bt->device) return fail(NTT_EINVAL, "batch belongs to device %d, current device is %d", bt->device, dev);
     if (ws_bytes < bt->big_ws || (bt->big_ws && !workspace))
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", bt->big_ws, ws_bytes);
-    for (const auto& g : bt->groups) {
+    unsigned char* ws = (unsigned char*)workspace;
+    Fork fork(stream, (int)bt->groups.size() + (bt->big.empty() ? 0 : 1));
+    int rc = fork.begin();
+    if (rc) return rc;
+    for (size_t k = 0; k < bt->groups.size(); ++k) {
+      const auto& g = bt->groups[k];
+      const hipStream_t st = fork.lane((int)k);
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = (const FusedItem*)bt->ditems + g.first;
-      fb.park = workspace;
+      fb.park = ws;  // this launch's own park area
       fb.count = (int)g.count;
-      if (g.wb == kF64Group || g.wb == kF64BandGroup)
-        HIP_TRY(launch_fused_f64(g.cls, g.wb == kF64BandGroup, fb, fused_grid(64, g.cls, g.count, bt->cus), stream));
-      else HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), stream));
+      if (g.wb == kF64Group || g.wb == kF64BandGroup) {
+        HIP_TRY(launch_fused_f64(g.cls, g.wb == kF64BandGroup, fb, fused_grid(64, g.cls, g.count, bt->cus), st));
+      } else {
+        HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, bt->cus), st));
+        ws += fused_launch_ws(g.wb, g.cls, g.count, bt->cus);
+      }
     }
     for (const auto& b : bt->big) {
-      int rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, workspace, stream);
+      rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, ws,
+                                 fork.lane((int)bt->groups.size()));
       if (rc) return rc;
     }
+    rc = fork.join();
+    if (rc) return rc;
     return ok();
   } catch (...) {
     return fail(NTT_EDEVICE, "exception in polymul_batch_launch");

@@ -146,3 +146,34 @@ def test_split_truncated_products(fresh, p, la, lb, L, d):
     S = 1 << (L - d)
     say("split product p=%d la=%d lb=%d: %d of %d sub-problems" % (p, la, lb, -(-(la + lb - 1) // S), 1 << d))
     assert_equal_u(ntt.to_numpy(ntt.polymul(ntt.to_device(a), ntt.to_device(b), p)), want, "truncated split product")
+
+
+def test_batch_fork_choices_agree(fresh):
+    """A batch of every size class and of two-pass products, its launches forked onto
+    streams of their own (the default) or all on the caller's stream: the same products,
+    equal to the oracle's, through one-call batches and reusable handles."""
+    torch = fresh
+    primes = (998244353, 2013265921, 4611685941117976577)
+    shapes = [(primes[i % 3], la, lb) for i, (la, lb) in enumerate(
+        [(100, 29), (700, 300), (2000, 2049), (4000, 4000), (9000, 7000), (20000, 30000), (1 << 15, 1 << 15),
+         (40000, 25000), (70000, 60000), (1 << 17, 5), (3, 1 << 18)])]
+    pairs, args = [], []
+    for i, (p, la, lb) in enumerate(shapes):
+        a = inputs.residues(p, la, inputs.CFG_TEST, 1500 + i, 0)
+        b = inputs.residues(p, lb, inputs.CFG_TEST, 1500 + i, 1)
+        pairs.append((ntt.to_device(a), ntt.to_device(b)))
+        args.append((a, b, p))
+    want = [oracle.polymul_ntt(a, b, p) for a, b, p in args]
+    for fork in (1, 0):
+        ntt.tune_set("batch.fork", fork)
+        say("batch of %d products, batch.fork=%d" % (len(shapes), fork))
+        got = ntt.polymul_batch(pairs, [s[0] for s in shapes])
+        outs = [torch.full_like(g, -1) for g in got]
+        bt = ntt.Batch(pairs, [s[0] for s in shapes], outs)
+        for _ in range(2):
+            bt()
+        torch.cuda.synchronize()
+        for i in range(len(shapes)):
+            assert_equal_u(ntt.to_numpy(got[i]), want[i], "batch item %d, batch.fork=%d" % (i, fork))
+            assert_equal_u(ntt.to_numpy(outs[i]), want[i], "handle item %d, batch.fork=%d" % (i, fork))
+        bt.close()
