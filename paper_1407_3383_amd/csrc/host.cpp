@@ -592,7 +592,15 @@ struct Staging {
 
 struct DeviceCtx {
   std::mutex mu;
-  std::map<hipStream_t, std::vector<hipStream_t>> lanes;  // fork streams per caller stream
+  // Fork streams of batch calls (class Fork): kForkLanes per caller stream, for the
+  // kForkCallers caller streams used most recently (a bounded set: callers' streams come
+  // and go, these are never destroyed); an older caller's lanes pass to a new caller.
+  struct Lanes {
+    std::vector<hipStream_t> s;
+    uint64_t used = 0;
+  };
+  std::map<hipStream_t, Lanes> lanes;
+  uint64_t lane_clock = 0;
   std::map<std::pair<uint64_t, uint32_t>, ntt_plan*> plans;
   Staging ring[8];
   unsigned next = 0;
@@ -1348,10 +1356,13 @@ size_t batch_scratch(const std::vector<ProductShape>& shapes, int cus, size_t* n
 
 // The independent launches of one batch call (one per size class, and the two-pass
 // products as one sequence): unit 0 runs on the caller's stream, unit k > 0 on a
-// stream forked from it (created once per caller stream, default priority) and joined
+// stream forked from it (at most kForkLanes per caller, default priority) and joined
 // back into it, so that classes that fill few CUs and the two-pass products overlap.
 // Everything stays on the caller's stream while a graph is being captured, for a single
 // unit, or with the tuning choice batch.fork = 0.
+constexpr int kForkLanes = 8;
+constexpr size_t kForkCallers = 8;
+
 class Fork {
  public:
   Fork(hipStream_t s, int units) : main_(s), units_(units) {}
@@ -1365,20 +1376,35 @@ class Fork {
     DeviceCtx* ctx = device_ctx(dev);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
-      std::vector<hipStream_t>& v = ctx->lanes[main_];
-      while ((int)v.size() < units_ - 1) {
+      auto it = ctx->lanes.find(main_);
+      if (it == ctx->lanes.end()) {
+        DeviceCtx::Lanes moved;
+        if (ctx->lanes.size() >= kForkCallers) {  // hand the least recently used caller's lanes over
+          auto old = ctx->lanes.begin();
+          for (auto j = ctx->lanes.begin(); j != ctx->lanes.end(); ++j)
+            if (j->second.used < old->second.used) old = j;
+          moved = std::move(old->second);
+          ctx->lanes.erase(old);
+        }
+        it = ctx->lanes.emplace(main_, std::move(moved)).first;
+      }
+      std::vector<hipStream_t>& v = it->second.s;
+      it->second.used = ++ctx->lane_clock;
+      const int want = std::min(units_ - 1, kForkLanes);
+      while ((int)v.size() < want) {
         hipStream_t t = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));  // default priority
         v.push_back(t);
       }
-      lanes_.assign(v.begin(), v.begin() + (units_ - 1));
+      lanes_.assign(v.begin(), v.begin() + want);
     }
     HIP_TRY(hipEventCreateWithFlags(&e0_, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(e0_, main_));
     for (hipStream_t l : lanes_) HIP_TRY(hipStreamWaitEvent(l, e0_, 0));
     return NTT_OK;
   }
-  hipStream_t lane(int k) const { return k == 0 || lanes_.empty() ? main_ : lanes_[k - 1]; }
+  // unit k > 0 on lane (k - 1) mod kForkLanes: units beyond the lanes share them in turn
+  hipStream_t lane(int k) const { return k == 0 || lanes_.empty() ? main_ : lanes_[(k - 1) % lanes_.size()]; }
   int join() {
     for (hipStream_t l : lanes_) {
       hipEvent_t e = nullptr;
@@ -1545,7 +1571,9 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
     unsigned char* ws = (unsigned char*)workspace + align256(nfused * sizeof(FusedItem));
     const bool any_big = nfused < count && std::any_of(shapes.begin(), shapes.end(),
                                                        [](const ProductShape& s) { return s.L >= 0 && !s.fused; });
-    Fork fork(stream, (int)groups.size() + (any_big ? 1 : 0));
+    // unit 0 (the caller's stream): the multi-pass sequence, the longest; then the groups
+    const int g0 = any_big ? 1 : 0;
+    Fork fork(stream, (int)groups.size() + g0);
     int rc = fork.begin();
     if (rc) return rc;
     for (size_t k = 0; k < groups.size(); ++k) {
@@ -1555,7 +1583,7 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
       fb.items = ditems + g.first;
       fb.park = ws;  // this launch's own park area
       fb.count = (int)g.count;
-      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, cus), fork.lane((int)k)));
+      HIP_TRY(launch_fused(g.wb, g.cls, fb, fused_grid(g.wb, g.cls, g.count, cus), fork.lane((int)k + g0)));
       ws += fused_launch_ws(g.wb, g.cls, g.count, cus);
     }
     for (size_t i = 0; i < count; ++i) {
@@ -1564,8 +1592,7 @@ int polymul_modp_batch(const ntt_polymul_desc* d, size_t count, void* workspace,
       ntt_plan* pl = nullptr;
       rc = cached_plan(s.p, (uint32_t)s.L, &pl);
       if (rc) return rc;
-      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, ws,
-                                 fork.lane((int)groups.size()));
+      rc = run_multipass_product(pl, d[i].a, d[i].la, d[i].b, d[i].lb, d[i].c, s.lc, false, ws, fork.lane(0));
       if (rc) return rc;
     }
     rc = fork.join();
@@ -1683,12 +1710,14 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
     if (ws_bytes < bt->big_ws || (bt->big_ws && !workspace))
       return fail(NTT_ENOMEM, "workspace of %zu bytes needed, %zu given", bt->big_ws, ws_bytes);
     unsigned char* ws = (unsigned char*)workspace;
-    Fork fork(stream, (int)bt->groups.size() + (bt->big.empty() ? 0 : 1));
+    // unit 0 (the caller's stream): the multi-pass sequence, the longest; then the groups
+    const int g0 = bt->big.empty() ? 0 : 1;
+    Fork fork(stream, (int)bt->groups.size() + g0);
     int rc = fork.begin();
     if (rc) return rc;
     for (size_t k = 0; k < bt->groups.size(); ++k) {
       const auto& g = bt->groups[k];
-      const hipStream_t st = fork.lane((int)k);
+      const hipStream_t st = fork.lane((int)k + g0);
       FusedBatch fb;
       memset(&fb, 0, sizeof(fb));
       fb.items = (const FusedItem*)bt->ditems + g.first;
@@ -1702,8 +1731,7 @@ int polymul_batch_launch(const ntt_batch* bt, void* workspace, size_t ws_bytes, 
       }
     }
     for (const auto& b : bt->big) {
-      rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, ws,
-                                 fork.lane((int)bt->groups.size()));
+      rc = run_multipass_product(b.pl, b.a, b.la, b.b, b.lb, b.c, b.lc, false, ws, fork.lane(0));
       if (rc) return rc;
     }
     rc = fork.join();
