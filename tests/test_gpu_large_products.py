@@ -48,3 +48,23 @@ def test_native_server_large_requests():
     for r, w in zip(reqs, want):
         assert_equal_u(r.result, w, "native request %d (p=%d, L=%d) vs oracle" % (r.rid, r.p, r.a.size))
     srv.close()
+
+
+@pytest.mark.parametrize("p,la,lb", [(469762049, 1 << 25, (1 << 25) + 1 - 1), (469762049, (1 << 26) - 5, 6),
+                                     (nt.largest_prime_below(62, 32), 1 << 23, (1 << 23) - 1)])
+def test_products_at_maximum_length(p, la, lb):
+    """Products whose transform is the longest a plan takes (2^26 words for 32-bit
+    primes): c(x) = a(x) b(x) at random points x (an identity at any size, independent
+    of any transform), and the lowest and highest coefficients."""
+    torch_cuda()
+    a = inputs.residues(p, la, inputs.CFG_TEST, 9100, 0)
+    b = inputs.residues(p, lb, inputs.CFG_TEST, 9100, 1)
+    say("maximum-length product p=%d la=%d lb=%d" % (p, la, lb))
+    c = ntt.to_numpy(ntt.polymul(ntt.to_device(a), ntt.to_device(b), p))
+    assert c.size == la + lb - 1
+    xs = [int(v) for v in inputs.residues(p, 6, inputs.CFG_TEST, 9101, 0)]
+    ea, eb, ec = oracle.horner_many(a, p, xs), oracle.horner_many(b, p, xs), oracle.horner_many(c, p, xs)
+    for k in range(len(xs)):
+        assert int(ec[k]) == int(ea[k]) * int(eb[k]) % p, "product at x = %d" % xs[k]
+    assert int(c[0]) == int(a[0]) * int(b[0]) % p
+    assert int(c[-1]) == int(a[-1]) * int(b[-1]) % p

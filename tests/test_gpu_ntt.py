@@ -97,3 +97,22 @@ def test_validate_flag_rejects_noncanonical():
     assert e.value.code == ntt.NTT_ERANGE
     x[17] = p - 1
     plan.forward(ntt.to_device(x))
+
+
+@pytest.mark.parametrize("p,log2n", [(469762049, 26), (2013265921, 25), (P62, 24)])
+def test_maximum_length_transforms(p, log2n):
+    """The longest transforms the plans take (2^26 words; the column pass then runs its
+    rounds across workgroups): evaluations at random points of the TFT-order output,
+    the first and last values, and the round trip."""
+    torch_cuda()
+    n = 1 << log2n
+    plan, w = _plan(p, log2n, ntt.NTT_BITREV_OUT | ntt.NTT_BITREV_IN)
+    x = inputs.residues(p, n, inputs.CFG_TEST, 90 + log2n)
+    say("ntt maximum p=%d log2n=%d passes=%d" % (p, log2n, plan.info.passes))
+    X = plan.forward(ntt.to_device(x))
+    Xh = ntt.to_numpy(X)
+    rng = np.random.default_rng(log2n + 1)
+    idx = np.concatenate([[0, 1, n - 1], rng.integers(0, n, size=8)])
+    pts = [pow(w, oracle.bitrev(int(i), log2n), p) for i in idx]
+    assert_equal_u(Xh[idx], oracle.horner_many(x, p, pts), "maximum-length forward at sampled points")
+    assert_equal_u(ntt.to_numpy(plan.inverse(X)), x, "maximum-length roundtrip")
