@@ -59,6 +59,20 @@ __device__ __forceinline__ TwPair<T> ldtw(gcptr<TwPair<T>> p) {
   t.ws = p->ws;
   return t;
 }
+// The same from an address that is the same in every lane, read through the constant
+// address space: a scalar load into scalar registers.  Its wait is on the LDS/scalar
+// counter, not on the vector-memory counter, so it does not wait for the operand
+// loads issued before it.  Only for tables that no kernel writes.
+template <typename T>
+using kcptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ TwPair<T> ldtw_s(gcptr<TwPair<T>> p) {
+  const kcptr<TwPair<T>> q = (kcptr<TwPair<T>>)(uintptr_t)(const TwPair<T>*)p;
+  TwPair<T> t;
+  t.w = q->w;
+  t.ws = q->ws;
+  return t;
+}
 
 template <typename T>
 struct Arith;

@@ -65,7 +65,8 @@ __device__ __forceinline__ void cluster_inv(const Arith<T>& ar, T* x, const TwPa
 // b0 (so at cluster stage u it is (b0 << u) | vv): w[2^u - 1 + vv].
 // UNIFORM: b0 is the same in every lane of the wave; the twiddles are then kept in
 // scalar registers.
-template <typename T, int R, bool UNIFORM = false>
+// SCALAR (with UNIFORM): scalar loads (ldtw_s) instead of vector loads and moves.
+template <typename T, int R, bool UNIFORM = false, bool SCALAR = false>
 __device__ __forceinline__ void cluster_twiddles(TwPair<T>* w, gcptr<TwPair<T>> tw, int d, int t0, uint32_t h,
                                                  uint32_t b0) {
 #pragma unroll
@@ -74,8 +75,12 @@ __device__ __forceinline__ void cluster_twiddles(TwPair<T>* w, gcptr<TwPair<T>> 
     gcptr<TwPair<T>> p = tw + ((1u << (d + t)) + ((h << t) | (b0 << u)));
 #pragma unroll
     for (int vv = 0; vv < (1 << u); ++vv) {
-      const TwPair<T> x = ldtw<T>(p + vv);
-      w[(1 << u) - 1 + vv] = UNIFORM ? uni(x) : x;
+      if constexpr (UNIFORM && SCALAR) {
+        w[(1 << u) - 1 + vv] = ldtw_s<T>(p + vv);
+      } else {
+        const TwPair<T> x = ldtw<T>(p + vv);
+        w[(1 << u) - 1 + vv] = UNIFORM ? uni(x) : x;
+      }
     }
   }
 }
@@ -111,7 +116,10 @@ __device__ __forceinline__ void fwd_G(const Arith<T>& ar, T* const (&sv)[NV], in
 // Rounds W1..W3 of block B = wave id (or of block `blk` when it is given: a wave
 // may own several blocks); the result stays in x[v][16] with
 // x[v][4 k + c] = element 1024 B + 4 (lane + 64 k) + c.
-template <typename T, int LAZY, int NV, int M>
+// PF: each round's twiddles are requested one round ahead (W2's before W1's
+// arithmetic, all of W3's before W2's), so that their L2 latency overlaps the round
+// before; without it every round waits for its own twiddles.
+template <typename T, int LAZY, int NV, int M, bool PF = false>
 __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], int d, uint32_t h,
                                       gcptr<TwPair<T>> tw, T (&x)[NV][16], int blk = -1) {
   const int tid = opaque_tid();
@@ -122,6 +130,8 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
   TwPair<T> w[15];
   // W1: bits 9..6; twiddles uniform across the wave.
   cluster_twiddles<T, 4, true>(w, tw, d, M - 10, h, B);
+  TwPair<T> w2[PF ? 15 : 1];
+  if constexpr (PF) cluster_twiddles<T, 4>(w2, tw, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
   {
     const int lb = lbase + lane + (lane >> 5);
 #pragma unroll
@@ -135,17 +145,25 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
       for (int c = 0; c < 16; ++c) sv[v][lb + c * 66] = x[v][c];
   }
   wave_sync();
+  TwPair<T> w3p[PF ? 4 : 1][3];
+  if constexpr (PF) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cluster_twiddles<T, 2>(w3p[k], tw, d, M - 2, h, (B << 8) | (uint32_t)(lane + 64 * k));
+  }
   // W2: bits 5..2.
   {
     const int h4 = lane >> 2, l2 = lane & 3;
-    cluster_twiddles<T, 4>(w, tw, d, M - 6, h, (B << 4) | (uint32_t)h4);
+    if constexpr (!PF) cluster_twiddles<T, 4>(w, tw, d, M - 6, h, (B << 4) | (uint32_t)h4);
     const int e0 = base + 64 * h4 + l2;
     const int lb = e0 + (e0 >> 5);  // 4 c + l2 < 32 iff c < 8, since l2 < 4
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int c = 0; c < 16; ++c) x[v][c] = sv[v][lb + 4 * c + (c >> 3)];  // lidx(e0 + 4 c)
-    cluster_fwd<T, LAZY, 4, NV>(ar, x, 0, w);
+    if constexpr (PF)
+      cluster_fwd<T, LAZY, 4, NV>(ar, x, 0, w2);
+    else
+      cluster_fwd<T, LAZY, 4, NV>(ar, x, 0, w);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -157,7 +175,12 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
   for (int k = 0; k < 4; ++k) {
     const int g = lane + 64 * k;
     TwPair<T> w3[3];
-    cluster_twiddles<T, 2>(w3, tw, d, M - 2, h, (B << 8) | (uint32_t)g);
+    if constexpr (PF) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w3[c] = w3p[k][c];
+    } else {
+      cluster_twiddles<T, 2>(w3, tw, d, M - 2, h, (B << 8) | (uint32_t)g);
+    }
     const int e0 = base + 4 * g;
     const int lb = e0 + (e0 >> 5);
     T y[NV][4];
@@ -175,7 +198,9 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
 
 // ------------------------------------------------------------------ inverse
 // Rounds W3'..W1' from registers (layout of fwd_W), result stored to LDS.
-template <typename T, int LAZY, int M>
+// PF: the twiddles of W3' and W2' are requested together at the start, and those of
+// W1' before the arithmetic of W2' (as in fwd_W).
+template <typename T, int LAZY, int M, bool PF = false>
 __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi,
                                       T (&x)[16], int blk = -1) {
   const int tid = opaque_tid();
@@ -183,12 +208,23 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
   const uint32_t B = blk >= 0 ? (uint32_t)blk : (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
   const int base = (int)B << 10;
   const int lbase = base + ((int)B << 5);
+  TwPair<T> w3p[PF ? 4 : 1][3], w2[PF ? 15 : 1];
+  if constexpr (PF) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cluster_twiddles<T, 2>(w3p[k], twi, d, M - 2, h, (B << 8) | (uint32_t)(lane + 64 * k));
+    cluster_twiddles<T, 4>(w2, twi, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
+  }
   // W3': bits 1..0.
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int g = lane + 64 * k;
     TwPair<T> w3[3];
-    cluster_twiddles<T, 2>(w3, twi, d, M - 2, h, (B << 8) | (uint32_t)g);
+    if constexpr (PF) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w3[c] = w3p[k][c];
+    } else {
+      cluster_twiddles<T, 2>(w3, twi, d, M - 2, h, (B << 8) | (uint32_t)g);
+    }
     cluster_inv<T, LAZY, 2>(ar, x + 4 * k, w3);
     const int e0 = base + 4 * g;
     const int lb = e0 + (e0 >> 5);
@@ -197,26 +233,32 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
   }
   wave_sync();
   TwPair<T> w[15];
+  // (kept in vector registers: moved to scalar registers, they would be waited for
+  // inside W2')
+  if constexpr (PF) cluster_twiddles<T, 4>(w, twi, d, M - 10, h, B);
   // W2': bits 5..2.
   {
     const int h4 = lane >> 2, l2 = lane & 3;
-    cluster_twiddles<T, 4>(w, twi, d, M - 6, h, (B << 4) | (uint32_t)h4);
+    if constexpr (!PF) cluster_twiddles<T, 4>(w, twi, d, M - 6, h, (B << 4) | (uint32_t)h4);
     const int e0 = base + 64 * h4 + l2;
     const int lb = e0 + (e0 >> 5);
 #pragma unroll
     for (int c = 0; c < 16; ++c) x[c] = sa[lb + 4 * c + (c >> 3)];
-    cluster_inv<T, LAZY, 4>(ar, x, w);
+    if constexpr (PF)
+      cluster_inv<T, LAZY, 4>(ar, x, w2);
+    else
+      cluster_inv<T, LAZY, 4>(ar, x, w);
 #pragma unroll
     for (int c = 0; c < 16; ++c) sa[lb + 4 * c + (c >> 3)] = x[c];
   }
   wave_sync();
   // W1': bits 9..6; twiddles uniform across the wave.
-  cluster_twiddles<T, 4, true>(w, twi, d, M - 10, h, B);
+  if constexpr (!PF) cluster_twiddles<T, 4, true>(w, twi, d, M - 10, h, B);
   {
     const int lb = lbase + lane + (lane >> 5);
 #pragma unroll
     for (int c = 0; c < 16; ++c) x[c] = sa[lb + c * 66];
-    cluster_inv<T, LAZY, 4, true>(ar, x, w);
+    cluster_inv<T, LAZY, 4, !PF>(ar, x, w);
 #pragma unroll
     for (int c = 0; c < 16; ++c) sa[lb + c * 66] = x[c];
   }

@@ -272,12 +272,16 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   // partial is completed from the zero coefficients when lam < nsub (d = 2, lam = 3)
   const int lam = (int)((lc + S - 1) / S < (uint64_t)nsub ? (lc + S - 1) / S : (uint64_t)nsub);
   T* const sv2[2] = {sa, sb};
+  constexpr bool kWavePF = true;
 
-  // G' (top inverse stages) of sub-problem hp on the thread's clusters; hands each
-  // finished value to `sink(e, j, value)`.
-  auto finish = [&](int hp, int t0, auto&& sink) {
-    TwPair<T> wi[C > 1 ? C - 1 : 1];
-    if constexpr (R > 0) cluster_twiddles<T, R, true>(wi, twi, d, 0, (uint32_t)hp, 0u);
+  // G' (top inverse stages) of sub-problem hp on the thread's clusters, with its
+  // twiddles wi (requested by finish_twiddles ahead of the operand loads, through
+  // scalar loads whose wait does not include those loads); hands each finished value
+  // to `sink(e, j, value)`.
+  auto finish_twiddles = [&](TwPair<T>* wi, int hp) {
+    if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wi, twi, d, 0, (uint32_t)hp, 0u);
+  };
+  auto finish = [&](const TwPair<T>* wi, int t0, auto&& sink) {
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int q = t0 + i * NT;
@@ -328,15 +332,21 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   };
   for (int h = 0; h < lam; ++h) {
     const int t0 = opaque_tid();
-    request_fold_inputs();
-    // ---- boundary phase: G' of h-1 and park, fold + G of h
+    // ---- boundary phase: G' of h-1 and park, fold + G of h.  The twiddles and fold
+    // factors (scalar loads) are requested before the operands.
+    TwPair<T> wi[C > 1 ? C - 1 : 1];
     if constexpr (MAXD > 0) {
-      if (h > 0) finish(h - 1, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
+      if (h > 0) finish_twiddles(wi, h - 1);
+    }
+    const gcptr<TwPair<T>> fah = &pc->fa[h][0], fbh = &pc->fb[h][0];
+    const TwPair<T> fa1 = ldtw_s<T>(fah + 1), fb0 = ldtw_s<T>(fbh), fb1 = ldtw_s<T>(fbh + 1);
+    TwPair<T> wf[C > 1 ? C - 1 : 1];
+    if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wf, tw, d, 0, (uint32_t)h, 0u);
+    request_fold_inputs();
+    if constexpr (MAXD > 0) {
+      if (h > 0) finish(wi, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
     }
     {
-      const TwPair<T> fa1 = uni(ldtw<T>(&pc->fa[h][1])), fb0 = uni(ldtw<T>(&pc->fb[h][0])), fb1 = uni(ldtw<T>(&pc->fb[h][1]));
-      TwPair<T> wf[C > 1 ? C - 1 : 1];
-      if constexpr (R > 0) cluster_twiddles<T, R, true>(wf, tw, d, 0, (uint32_t)h, 0u);
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
         const int q = t0 + i * NT;
@@ -380,7 +390,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
     // ---- wave phase
     if ((opaque_tid() >> 6) < (1 << (M - 10))) {
       T x[2][16];
-      fwd_W<T, LAZY, 2, M>(ar, sv2, d, (uint32_t)h, tw, x);
+      fwd_W<T, LAZY, 2, M, kWavePF>(ar, sv2, d, (uint32_t)h, tw, x);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         T xa = x[0][i], yb = x[1][i];
@@ -394,38 +404,45 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         if constexpr (LAZY != kLazy) z = ar.red1(z);
         x[0][i] = z;
       }
-      inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0]);
+      inv_W<T, LAZY, M, kWavePF>(ar, sa, d, (uint32_t)h, twi, x[0]);
     }
     __syncthreads();
   }
   // ---- last boundary: G' of the last sub-problem and the recombination
   {
     const int t0 = opaque_tid();
+    // Recombination twiddles and completion factors first (from L2), then the parked
+    // partials, all before any output store (a load placed after a store would wait
+    // for the store as well).  Each partial's loads form one block under one uniform
+    // test, not a branch per load (a branch per load makes every join wait for all
+    // loads in flight).
+    TwPair<T> wi[C > 1 ? C - 1 : 1];
+    finish_twiddles(wi, lam - 1);
+    TwPair<T> w1, w2, w3, k0, k1, k2;
+    if constexpr (MAXD > 0) {
+      const gcptr<TwPair<T>> kt = &pc->tft2[0];
+      w1 = ldtw_s<T>(twi + 1);
+      w2 = ldtw_s<T>(twi + 2);
+      w3 = ldtw_s<T>(twi + 3);
+      k0 = ldtw_s<T>(kt);
+      k1 = ldtw_s<T>(kt + 1);
+      k2 = ldtw_s<T>(kt + 2);
+    }
     T q0[EPT], q1[EPT], q2[EPT];
     if constexpr (MAXD > 0) {
 #pragma unroll
-      for (int i = 0; i < CPT; ++i)
+      for (int e = 0; e < EPT; ++e) q0[e] = q1[e] = q2[e] = (T)0;
+      auto load_partial = [&](T(&q)[EPT], int k) {
 #pragma unroll
-        for (int cc = 0; cc < C; ++cc) {
-          const int e = i * C + cc;
-          const int j = t0 + i * NT + 1024 * cc;
-          q0[e] = d >= 1 ? park[j] : (T)0;
-          q1[e] = d >= 2 ? park[S + j] : (T)0;
-          q2[e] = (d >= 2 && lam == 4) ? park[2 * S + j] : (T)0;
-        }
+        for (int i = 0; i < CPT; ++i)
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) q[i * C + cc] = park[(size_t)k * S + (t0 + i * NT + 1024 * cc)];
+      };
+      if (d >= 1) load_partial(q0, 0);
+      if (d >= 2) load_partial(q1, 1);
+      if (d >= 2 && lam == 4) load_partial(q2, 2);
     }
-    // recombination twiddles and completion factors, loaded before any output store
-    // (a load placed after a store would wait for the store as well)
-    TwPair<T> w1, w2, w3, k0, k1, k2;
-    if constexpr (MAXD > 0) {
-      w1 = uni(ldtw<T>(twi + 1));
-      w2 = uni(ldtw<T>(twi + 2));
-      w3 = uni(ldtw<T>(twi + 3));
-      k0 = uni(ldtw<T>(&pc->tft2[0]));
-      k1 = uni(ldtw<T>(&pc->tft2[1]));
-      k2 = uni(ldtw<T>(&pc->tft2[2]));
-    }
-    finish(lam - 1, t0, [&](int e, int j, T v) {
+    finish(wi, t0, [&](int e, int j, T v) {
       const uint64_t jj = (uint64_t)j;
       if (d == 0) {
         if (jj < lc) c[jj] = canon_from_inv<LAZY>(ar, v);
