@@ -128,8 +128,8 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
   const int base = (int)B << 10;
   const int lbase = base + ((int)B << 5);  // lidx(base)
   TwPair<T> w[15];
-  // W1: bits 9..6; twiddles uniform across the wave.
-  cluster_twiddles<T, 4, true>(w, tw, d, M - 10, h, B);
+  // W1: bits 9..6; twiddles uniform across the wave (scalar loads with PF).
+  cluster_twiddles<T, 4, true, PF>(w, tw, d, M - 10, h, B);
   TwPair<T> w2[PF ? 15 : 1];
   if constexpr (PF) cluster_twiddles<T, 4>(w2, tw, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
   {
@@ -197,23 +197,35 @@ __device__ __forceinline__ void fwd_W(const Arith<T>& ar, T* const (&sv)[NV], in
 }
 
 // ------------------------------------------------------------------ inverse
+// Twiddles of W3' and W2' requested ahead of inv_W (with PF), for instance before the
+// entry-wise product that precedes it.
+template <typename T>
+struct InvWTw {
+  TwPair<T> w3[4][3];
+  TwPair<T> w2[15];
+};
+template <typename T, int M>
+__device__ __forceinline__ void inv_W_twiddles(InvWTw<T>& t, int d, uint32_t h, gcptr<TwPair<T>> twi) {
+  const int tid = opaque_tid();
+  const int lane = tid & 63;
+  const uint32_t B = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) cluster_twiddles<T, 2>(t.w3[k], twi, d, M - 2, h, (B << 8) | (uint32_t)(lane + 64 * k));
+  cluster_twiddles<T, 4>(t.w2, twi, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
+}
+
 // Rounds W3'..W1' from registers (layout of fwd_W), result stored to LDS.
-// PF: the twiddles of W3' and W2' are requested together at the start, and those of
-// W1' before the arithmetic of W2' (as in fwd_W).
+// PF: the twiddles of W3' and W2' come from `pre` (inv_W_twiddles, same block), and
+// those of W1' are requested before the arithmetic of W2' (as in fwd_W).
 template <typename T, int LAZY, int M, bool PF = false>
 __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi,
-                                      T (&x)[16], int blk = -1) {
+                                      T (&x)[16], int blk = -1, const InvWTw<T>* pre = nullptr) {
   const int tid = opaque_tid();
   const int lane = tid & 63;
   const uint32_t B = blk >= 0 ? (uint32_t)blk : (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
   const int base = (int)B << 10;
   const int lbase = base + ((int)B << 5);
-  TwPair<T> w3p[PF ? 4 : 1][3], w2[PF ? 15 : 1];
-  if constexpr (PF) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) cluster_twiddles<T, 2>(w3p[k], twi, d, M - 2, h, (B << 8) | (uint32_t)(lane + 64 * k));
-    cluster_twiddles<T, 4>(w2, twi, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
-  }
+  (void)pre;
   // W3': bits 1..0.
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -221,7 +233,7 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
     TwPair<T> w3[3];
     if constexpr (PF) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) w3[c] = w3p[k][c];
+      for (int c = 0; c < 3; ++c) w3[c] = pre->w3[k][c];
     } else {
       cluster_twiddles<T, 2>(w3, twi, d, M - 2, h, (B << 8) | (uint32_t)g);
     }
@@ -245,7 +257,7 @@ __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t
 #pragma unroll
     for (int c = 0; c < 16; ++c) x[c] = sa[lb + 4 * c + (c >> 3)];
     if constexpr (PF)
-      cluster_inv<T, LAZY, 4>(ar, x, w2);
+      cluster_inv<T, LAZY, 4>(ar, x, pre->w2);
     else
       cluster_inv<T, LAZY, 4>(ar, x, w);
 #pragma unroll

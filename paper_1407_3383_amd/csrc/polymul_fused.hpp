@@ -391,6 +391,8 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
     if ((opaque_tid() >> 6) < (1 << (M - 10))) {
       T x[2][16];
       fwd_W<T, LAZY, 2, M, kWavePF>(ar, sv2, d, (uint32_t)h, tw, x);
+      InvWTw<T> itw;
+      if constexpr (kWavePF) inv_W_twiddles<T, M>(itw, d, (uint32_t)h, twi);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         T xa = x[0][i], yb = x[1][i];
@@ -404,7 +406,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
         if constexpr (LAZY != kLazy) z = ar.red1(z);
         x[0][i] = z;
       }
-      inv_W<T, LAZY, M, kWavePF>(ar, sa, d, (uint32_t)h, twi, x[0]);
+      inv_W<T, LAZY, M, kWavePF>(ar, sa, d, (uint32_t)h, twi, x[0], -1, &itw);
     }
     __syncthreads();
   }
