@@ -332,50 +332,59 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   };
   for (int h = 0; h < lam; ++h) {
     const int t0 = opaque_tid();
-    // ---- boundary phase: G' of h-1 and park, fold + G of h.  The twiddles and fold
-    // factors (scalar loads) are requested before the operands.
+    // ---- boundary phase: G' of h-1 and park, fold + G of h.  G''s twiddles (scalar
+    // loads, requested for every h so that no branch separates them from their use)
+    // go out before the operands, the fold's after G' (their scalar registers are not
+    // live at the same time).
     TwPair<T> wi[C > 1 ? C - 1 : 1];
-    if constexpr (MAXD > 0) {
-      if (h > 0) finish_twiddles(wi, h - 1);
-    }
-    const gcptr<TwPair<T>> fah = &pc->fa[h][0], fbh = &pc->fb[h][0];
-    const TwPair<T> fa1 = ldtw_s<T>(fah + 1), fb0 = ldtw_s<T>(fbh), fb1 = ldtw_s<T>(fbh + 1);
-    TwPair<T> wf[C > 1 ? C - 1 : 1];
-    if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wf, tw, d, 0, (uint32_t)h, 0u);
+    if constexpr (MAXD > 0) finish_twiddles(wi, h > 0 ? h - 1 : 0);
     request_fold_inputs();
     if constexpr (MAXD > 0) {
       if (h > 0) finish(wi, t0, [&](int, int j, T v) { park[(size_t)(h - 1) * S + j] = v; });
     }
     {
+      const gcptr<TwPair<T>> fah = &pc->fa[h][0], fbh = &pc->fb[h][0];
+      const TwPair<T> fa1 = ldtw_s<T>(fah + 1), fb0 = ldtw_s<T>(fbh), fb1 = ldtw_s<T>(fbh + 1);
+      TwPair<T> wf[C > 1 ? C - 1 : 1];
+      if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wf, tw, d, 0, (uint32_t)h, 0u);
 #pragma unroll
       for (int i = 0; i < CPT; ++i) {
         const int q = t0 + i * NT;
         T v[2][C];
+        if (nsub > 1 && !more_terms) {  // two terms per position: no branch per position
 #pragma unroll
-        for (int cc = 0; cc < C; ++cc) {
-          const int e = i * C + cc;
-          T fa = x0[e];
-          T fb = ar.red1(ar.shoup_u(y0[e], fb0.w, fb0.ws));
-          if (nsub > 1) {
-            fa = ar.red1(fa + ar.red1(ar.shoup_u(x1[e], fa1.w, fa1.ws)));
-            fb = ar.red1(fb + ar.red1(ar.shoup_u(y1[e], fb1.w, fb1.ws)));
+          for (int cc = 0; cc < C; ++cc) {
+            const int e = i * C + cc;
+            v[0][cc] = ar.red1(x0[e] + ar.red1(ar.shoup_u(x1[e], fa1.w, fa1.ws)));
+            v[1][cc] = ar.red1(ar.red1(ar.shoup_u(y0[e], fb0.w, fb0.ws)) + ar.red1(ar.shoup_u(y1[e], fb1.w, fb1.ws)));
           }
-          if (more_terms) {
-            const uint64_t j = (uint64_t)q + 1024u * cc;
-            for (int k = 2; k < nsub; ++k) {
-              const uint64_t idx = j + (uint64_t)k * S;
-              if (idx < la) {
-                const TwPair<T> f = ldtw<T>(&pc->fa[h][k]);
-                fa = ar.red1(fa + ar.red1(ar.shoup(a[idx], f.w, f.ws)));
-              }
-              if (idx < lb) {
-                const TwPair<T> f = ldtw<T>(&pc->fb[h][k]);
-                fb = ar.red1(fb + ar.red1(ar.shoup(b[idx], f.w, f.ws)));
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < C; ++cc) {
+            const int e = i * C + cc;
+            T fa = x0[e];
+            T fb = ar.red1(ar.shoup_u(y0[e], fb0.w, fb0.ws));
+            if (nsub > 1) {
+              fa = ar.red1(fa + ar.red1(ar.shoup_u(x1[e], fa1.w, fa1.ws)));
+              fb = ar.red1(fb + ar.red1(ar.shoup_u(y1[e], fb1.w, fb1.ws)));
+            }
+            if (more_terms) {
+              const uint64_t j = (uint64_t)q + 1024u * cc;
+              for (int k = 2; k < nsub; ++k) {
+                const uint64_t idx = j + (uint64_t)k * S;
+                if (idx < la) {
+                  const TwPair<T> f = ldtw<T>(&pc->fa[h][k]);
+                  fa = ar.red1(fa + ar.red1(ar.shoup(a[idx], f.w, f.ws)));
+                }
+                if (idx < lb) {
+                  const TwPair<T> f = ldtw<T>(&pc->fb[h][k]);
+                  fb = ar.red1(fb + ar.red1(ar.shoup(b[idx], f.w, f.ws)));
+                }
               }
             }
+            v[0][cc] = fa;
+            v[1][cc] = fb;
           }
-          v[0][cc] = fa;
-          v[1][cc] = fb;
         }
         if constexpr (R > 0) cluster_fwd<T, LAZY, R, 2, true>(ar, v, 0, wf);
         const int lb0 = lidx(q);
