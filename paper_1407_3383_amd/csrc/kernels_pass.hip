@@ -75,16 +75,19 @@ template <int C>
 __device__ __forceinline__ void row_factors(TwPair<uint32_t> (&D)[C], gcptr<TwPair<uint32_t>> t, int S, uint32_t Rr,
                                             uint32_t p) {
   const uint32_t mask = (1u << S) - 1, half = 1u << (S - 1);
+  // every scalar load first (their wait covers no vector load), then the negations
 #pragma unroll
   for (int c = 0; c < C; ++c) {
     const uint32_t e = ((uint32_t)c * Rr) & mask;
-    const uint32_t i = brev_u(e & (half - 1), S - 1);
-    TwPair<uint32_t> x = uni(ldtw<uint32_t>(t + (half + i)));
+    D[c] = ldtw_s<uint32_t>(t + (half + brev_u(e & (half - 1), S - 1)));
+  }
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const uint32_t e = ((uint32_t)c * Rr) & mask;
     if (e >= half) {
-      x.w = p - x.w;
-      x.ws = ~x.ws;
+      D[c].w = p - D[c].w;
+      D[c].ws = ~D[c].ws;
     }
-    D[c] = x;
   }
 }
 
@@ -110,7 +113,40 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     bool vec4 = false;
     if constexpr (sizeof(T) == 4 && sizeof(IN_T) <= 4)
       vec4 = C >= 4 && ((uintptr_t)(const IN_T*)in % (4 * sizeof(IN_T))) == 0 && (A.in_stride % 4) == 0;
-    if (vec4) {
+    // a full-width tile whose words all lie below A.valid: every load of the thread is
+    // requested before the first LDS store (one memory round trip per tile, not one per
+    // iteration of the loop below)
+    constexpr int IT4 = ((1 << TILELOG) >> 2) / NT;
+    bool staged = false;
+    if constexpr (sizeof(T) == 4 && sizeof(IN_T) == 4 && IT4 >= 1 && IT4 <= 8 && IT4 * 4 * NT == (1 << TILELOG)) {
+      const bool full_tile =
+          LC == LC0 && ((((uint64_t)(1 << K) - 1) << L2) + col0 + (uint64_t)C <= A.valid);
+      if (vec4 && full_tile) {
+        constexpr int lc4 = LC0 - 2;
+        uint4 q[IT4];
+#pragma unroll
+        for (int it = 0; it < IT4; ++it) {
+          const uint32_t idx = (uint32_t)(tid + it * NT);
+          const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
+          q[it] = *(const uint4*)((const IN_T*)in + (((uint64_t)r << L2) + col0 + cc));
+        }
+#pragma unroll
+        for (int it = 0; it < IT4; ++it) {
+          const uint32_t idx = (uint32_t)(tid + it * NT);
+          const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
+          T x[4] = {(T)q[it].x, (T)q[it].y, (T)q[it].z, (T)q[it].w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            T y = x[i];
+            if (scale) y = ar.red1(ar.shoup_u(y, sig.w, sig.ws));
+            s[(cc + i) * VS + lidx(r)] = y;
+          }
+        }
+        staged = true;
+      }
+    }
+    if (staged) {
+    } else if (vec4) {
       // runs of 4 columns as one 16-byte (8-byte for 16-bit limbs) access per thread
       const int lc4 = LC - 2;
 #pragma unroll 2
@@ -157,7 +193,33 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     const gcptr<T> in = gconst<T>(uni(A.in)) + vec * A.in_stride;
     bool vec4 = false;
     if constexpr (sizeof(T) == 4) vec4 = C >= 4 && ((uintptr_t)(const T*)in % 16) == 0 && (A.in_stride % 4) == 0;
-    if (vec4) {
+    // a full-width tile: every load of the thread before the first LDS store
+    constexpr int IT4 = ((1 << TILELOG) >> 2) / NT;
+    bool staged = false;
+    if constexpr (sizeof(T) == 4 && IT4 >= 1 && IT4 <= 8 && IT4 * 4 * NT == (1 << TILELOG)) {
+      if (vec4 && LC == LC0) {
+        constexpr int lc4 = LC0 - 2;
+        uint4 q[IT4];
+#pragma unroll
+        for (int it = 0; it < IT4; ++it) {
+          const uint32_t idx = (uint32_t)(tid + it * NT);
+          const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
+          q[it] = *(const uint4*)((const T*)in + (((uint64_t)r << L2) + col0 + cc));
+        }
+#pragma unroll
+        for (int it = 0; it < IT4; ++it) {
+          const uint32_t idx = (uint32_t)(tid + it * NT);
+          const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
+          s[cc * VS + lidx(r)] = q[it].x;
+          s[(cc + 1) * VS + lidx(r)] = q[it].y;
+          s[(cc + 2) * VS + lidx(r)] = q[it].z;
+          s[(cc + 3) * VS + lidx(r)] = q[it].w;
+        }
+        staged = true;
+      }
+    }
+    if (staged) {
+    } else if (vec4) {
       const int lc4 = LC - 2;
 #pragma unroll 2
       for (int idx = tid; idx < (cnt >> 2); idx += NT) {
@@ -285,21 +347,31 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
     const gcptr<TwPair<T>> hi = gconst<TwPair<T>>(uni(A.thi));
     const gcptr<T> ina = gconst<T>(uni(A.in)) + vec * A.in_stride + off;
     const gcptr<T> inb = gconst<T>(uni(A.in2)) + vec * A.in_stride + off;
+    // the row's words are requested first (from memory), the twiddles after them
+    // (scalar loads from L2, waited for separately)
+    constexpr int NV = KIND == 2 ? 2 : 1;
+    T vin[CPT][NV][C];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i)
+#pragma unroll
+      for (int cc = 0; cc < C; ++cc) {
+        const uint32_t j = (uint32_t)(t0 + i * NT + 1024 * cc);
+        vin[i][0][cc] = ina[j];
+        if constexpr (KIND == 2) vin[i][1][cc] = inb[j];
+      }
+    __builtin_amdgcn_sched_barrier(0);  // keeps the scheduler from moving the loads below
     TwPair<T> wf[C > 1 ? C - 1 : 1];
-    if constexpr (R > 0) cluster_twiddles<T, R, true>(wf, tw, 0, 0, 0u, 0u);
+    if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wf, tw, 0, 0, 0u, 0u);
     TwPair<T> D[C];
     if constexpr (sizeof(T) == 4) row_factors<C>(D, tw, S, Rr, ar.p);
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
       const int q = t0 + i * NT;
-      constexpr int NV = KIND == 2 ? 2 : 1;
       T v[NV][C];
 #pragma unroll
-      for (int cc = 0; cc < C; ++cc) {
-        const uint32_t j = (uint32_t)(q + 1024 * cc);
-        v[0][cc] = ina[j];
-        if constexpr (KIND == 2) v[1][cc] = inb[j];
-      }
+      for (int vv = 0; vv < NV; ++vv)
+#pragma unroll
+        for (int cc = 0; cc < C; ++cc) v[vv][cc] = vin[i][vv][cc];
       if constexpr (sizeof(T) == 4) {
         const TwPair<T> V = thread_factor(ar, (uint32_t)q * Rr, B, lo, hi, rcp32);
 #pragma unroll
@@ -383,7 +455,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
     const gcptr<TwPair<T>> ihi = gconst<TwPair<T>>(uni(A.tihi));
     const gptr<T> out = gmut<T>(uni(A.out)) + vec * A.out_stride + off;
     TwPair<T> wi[C > 1 ? C - 1 : 1];
-    if constexpr (R > 0) cluster_twiddles<T, R, true>(wi, twi, 0, 0, 0u, 0u);
+    if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wi, twi, 0, 0, 0u, 0u);
     TwPair<T> Di[C];
     if constexpr (sizeof(T) == 4) row_factors<C>(Di, twi, S, Rr, ar.p);
 #pragma unroll
