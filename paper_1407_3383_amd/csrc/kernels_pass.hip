@@ -113,31 +113,46 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
     bool vec4 = false;
     if constexpr (sizeof(T) == 4 && sizeof(IN_T) <= 4)
       vec4 = C >= 4 && ((uintptr_t)(const IN_T*)in % (4 * sizeof(IN_T))) == 0 && (A.in_stride % 4) == 0;
-    // a full-width tile whose words all lie below A.valid: every load of the thread is
-    // requested before the first LDS store (one memory round trip per tile, not one per
-    // iteration of the loop below)
+    // A full-width tile with A.valid a positive multiple of 4 (every run of 4 words then
+    // lies wholly below A.valid or wholly at or above it): every load of the thread is
+    // requested before the first LDS store, one memory round trip per tile instead of
+    // one per iteration of the loop below.  A run at or above A.valid loads the
+    // vector's first words (present, since A.valid >= 4) and is replaced by zeros, so
+    // that no branch separates the loads.
     constexpr int IT4 = ((1 << TILELOG) >> 2) / NT;
     bool staged = false;
-    if constexpr (sizeof(T) == 4 && sizeof(IN_T) == 4 && IT4 >= 1 && IT4 <= 8 && IT4 * 4 * NT == (1 << TILELOG)) {
-      const bool full_tile =
-          LC == LC0 && ((((uint64_t)(1 << K) - 1) << L2) + col0 + (uint64_t)C <= A.valid);
-      if (vec4 && full_tile) {
+    if constexpr (sizeof(T) == 4 && sizeof(IN_T) <= 4 && IT4 >= 1 && IT4 <= 8 && IT4 * 4 * NT == (1 << TILELOG)) {
+      if (vec4 && LC == LC0 && A.valid != 0 && (A.valid & 3) == 0) {
         constexpr int lc4 = LC0 - 2;
-        uint4 q[IT4];
+        using V4 = typename std::conditional<sizeof(IN_T) == 4, uint4, uint2>::type;
+        V4 q[IT4];
 #pragma unroll
         for (int it = 0; it < IT4; ++it) {
           const uint32_t idx = (uint32_t)(tid + it * NT);
           const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
-          q[it] = *(const uint4*)((const IN_T*)in + (((uint64_t)r << L2) + col0 + cc));
+          const uint64_t gi = ((uint64_t)r << L2) + col0 + cc;
+          q[it] = *(const V4*)((const IN_T*)in + (gi < A.valid ? gi : 0));
         }
 #pragma unroll
         for (int it = 0; it < IT4; ++it) {
           const uint32_t idx = (uint32_t)(tid + it * NT);
           const uint32_t r = idx >> lc4, cc = (idx & ((1u << lc4) - 1)) << 2;
-          T x[4] = {(T)q[it].x, (T)q[it].y, (T)q[it].z, (T)q[it].w};
+          const bool ok = ((uint64_t)r << L2) + col0 + cc < A.valid;
+          T x[4];
+          if constexpr (sizeof(IN_T) == 4) {
+            x[0] = q[it].x;
+            x[1] = q[it].y;
+            x[2] = q[it].z;
+            x[3] = q[it].w;
+          } else {
+            x[0] = q[it].x & 0xFFFFu;
+            x[1] = q[it].x >> 16;
+            x[2] = q[it].y & 0xFFFFu;
+            x[3] = q[it].y >> 16;
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            T y = x[i];
+            T y = ok ? x[i] : (T)0;
             if (scale) y = ar.red1(ar.shoup_u(y, sig.w, sig.ws));
             s[(cc + i) * VS + lidx(r)] = y;
           }
