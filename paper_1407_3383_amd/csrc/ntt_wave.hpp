@@ -205,17 +205,17 @@ struct InvWTw {
   TwPair<T> w2[15];
 };
 template <typename T, int M>
-__device__ __forceinline__ void inv_W_twiddles(InvWTw<T>& t, int d, uint32_t h, gcptr<TwPair<T>> twi) {
+__device__ __forceinline__ void inv_W_twiddles(InvWTw<T>& t, int d, uint32_t h, gcptr<TwPair<T>> twi, int blk = -1) {
   const int tid = opaque_tid();
   const int lane = tid & 63;
-  const uint32_t B = (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t B = blk >= 0 ? (uint32_t)blk : (uint32_t)__builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
   for (int k = 0; k < 4; ++k) cluster_twiddles<T, 2>(t.w3[k], twi, d, M - 2, h, (B << 8) | (uint32_t)(lane + 64 * k));
   cluster_twiddles<T, 4>(t.w2, twi, d, M - 6, h, (B << 4) | (uint32_t)(lane >> 2));
 }
 
 // Rounds W3'..W1' from registers (layout of fwd_W), result stored to LDS.
-// PF: the twiddles of W3' and W2' come from `pre` (inv_W_twiddles, same block), and
+// PF: the twiddles of W3' and W2' come from `pre` (inv_W_twiddles of the same block), and
 // those of W1' are requested before the arithmetic of W2' (as in fwd_W).
 template <typename T, int LAZY, int M, bool PF = false>
 __device__ __forceinline__ void inv_W(const Arith<T>& ar, T* sa, int d, uint32_t h, gcptr<TwPair<T>> twi,

@@ -540,7 +540,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
   const uint64_t la = it.la, lb = it.lb, lc = la + lb - 1;
   const int wave = __builtin_amdgcn_readfirstlane(opaque_tid() >> 6);
   // Montgomery scale of the entry-wise product (2^32 / N), applied to b's inputs
-  const TwPair<T> sig = uni(ldtw<T>(&pc->fb[0][0]));
+  const TwPair<T> sig = ldtw_s<T>(&pc->fb[0][0]);
 
   // fold inputs of one operand, requested ahead: lo[c] = x[q + 1024 c] (the upper
   // half, x[q + 1024 c + S], is read where it is added: HI items are rare, and holding
@@ -580,7 +580,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
       const int half = 16 >> u;
 #pragma unroll
       for (int vv = 0; vv < (1 << u); ++vv) {
-        const TwPair<T> ww = uni(ldtw<T>(tw + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv)));
+        const TwPair<T> ww = ldtw_s<T>(tw + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv));
 #pragma unroll
         for (int c2 = 0; c2 < half; ++c2) {
           const int cc = (vv << (5 - u)) + c2;
@@ -594,6 +594,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
   };
 
   request(a, la);
+  constexpr bool kW15PF = false;  // (the twiddles requested ahead push the spills from 124 to 312 bytes)
   for (int h = 0; h < 2; ++h) {
     // ---- A: fold, top stages, wave-local rounds kept in registers
     top_forward(h, a, la, false);
@@ -603,7 +604,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
     for (int k = 0; k < 2; ++k) {
       T* const sv1[1] = {sa};
       T x[1][16];
-      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+      fwd_W<T, LAZY, 1, M, kW15PF>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
 #pragma unroll
       for (int i = 0; i < 16; ++i) xa[k][i] = x[0][i];
     }
@@ -616,7 +617,9 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
     for (int k = 0; k < 2; ++k) {
       T* const sv1[1] = {sa};
       T x[1][16];
-      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+      fwd_W<T, LAZY, 1, M, kW15PF>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+      InvWTw<T> itw;
+      if constexpr (kW15PF) inv_W_twiddles<T, M>(itw, d, (uint32_t)h, twi, wave + 16 * k);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         T xv = xa[k][i], yv = x[0][i];
@@ -630,7 +633,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
         if constexpr (LAZY != kLazy) z = ar.red1(z);
         x[0][i] = z;
       }
-      inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0], wave + 16 * k);
+      inv_W<T, LAZY, M, kW15PF>(ar, sa, d, (uint32_t)h, twi, x[0], wave + 16 * k, &itw);
     }
     __syncthreads();
     // ---- G': top 5 inverse stages; the next sub-problem's a is requested first
@@ -646,7 +649,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
         const int half = 16 >> u;
 #pragma unroll
         for (int vv = 0; vv < (1 << u); ++vv) {
-          const TwPair<T> ww = uni(ldtw<T>(twi + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv)));
+          const TwPair<T> ww = ldtw_s<T>(twi + ((1u << (d + u)) + ((uint32_t)h << u) + (uint32_t)vv));
 #pragma unroll
           for (int c2 = 0; c2 < half; ++c2) {
             const int cc = (vv << (5 - u)) + c2;
@@ -659,7 +662,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
         for (int cc = 0; cc < C; ++cc) park[q + 1024 * cc] = v[cc];
       } else {
         // the last inverse stage across the two partials: (u0, u1) -> (u0 + u1, (u0 - u1) w)
-        const TwPair<T> w1 = uni(ldtw<T>(twi + 1));
+        const TwPair<T> w1 = ldtw_s<T>(twi + 1);
 #pragma unroll
         for (int cc = 0; cc < C; ++cc) {
           const uint32_t j = (uint32_t)(q + 1024 * cc);
