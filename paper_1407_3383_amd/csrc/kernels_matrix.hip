@@ -20,7 +20,7 @@ namespace nttgpu {
 
 namespace {
 
-constexpr int kMatThreads = 256;
+constexpr int kMatThreads = 512;
 
 // LDS layout, RS = (n + 1) KB words per matrix row: As[i RS + l KB + kk] = A[i][l] and
 // Bt[j RS + l KB + kk] = B[l][j] at frequency k0 + kk.  Consecutive l are KB words
