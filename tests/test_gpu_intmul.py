@@ -16,8 +16,10 @@ def _gpu_intmul(a, b):
 
 
 @pytest.mark.parametrize("na,nb", [(1, 1), (1, 2), (2, 2), (3, 7), (64, 64), (1000, 999), (4096, 4096),
-                                   (20000, 3), ((1 << 15), (1 << 15)), (70000, 65000)])
+                                   (20000, 3), ((1 << 15), (1 << 15)), (70000, 65000), (70001, 65003)])
 def test_intmul_against_python_int(na, nb):
+    # (70000, 65000) and (70001, 65003): two-pass transforms whose column pass reads whole
+    # runs of 4 limbs, or ends inside one (the per-run path of the column kernel)
     a = inputs.limbs16(na, inputs.CFG_TEST, na, 0)
     b = inputs.limbs16(nb, inputs.CFG_TEST, nb, 1)
     say("intmul na=%d nb=%d" % (na, nb))
@@ -64,7 +66,8 @@ def _gpu_intmul32(a16, b16):
 
 
 @pytest.mark.parametrize("na,nb", [(2, 2), (2, 4), (6, 14), (128, 128), (2000, 1998), (8192, 8192),
-                                   (40000, 6), ((1 << 15), (1 << 15)), (70000, 65000), (1 << 17, 1 << 16)])
+                                   (40000, 6), ((1 << 15), (1 << 15)), (70000, 65000), (70002, 65006),
+                                   (1 << 17, 1 << 16)])
 def test_intmul32_against_python_int(na, nb):
     # na, nb 16-bit limbs (even): the same integers read as 32-bit chunks
     a = inputs.limbs16(na, inputs.CFG_TEST, 3000 + na, 0)
