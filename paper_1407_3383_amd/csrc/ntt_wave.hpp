@@ -15,7 +15,8 @@
 // Stage t of the block (global stage d + t) uses twiddle TW[2^(d+t) + (h << t) + b],
 // b = the top t bits of the element's index inside the 2^M vector (see ntt_lds.hpp).
 // In G and W1 that index is the same for every lane of a wave, so those twiddles
-// come through the scalar cache.
+// are held in scalar registers (read by scalar loads where the caller asks for it:
+// their waits then do not cover the vector loads in flight).
 #pragma once
 #include "ntt_lds.hpp"
 
