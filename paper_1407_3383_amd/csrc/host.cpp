@@ -2254,12 +2254,15 @@ int polymat_run(uint64_t p, size_t n, const void* A, const void* B, size_t d, vo
       r.scale = 0;
       r.in_stride = N;
       r.valid = N;
+      PassJobs rows;  // the row passes of A and B as the two jobs of one launch
+      memset(&rows, 0, sizeof(rows));
       r.in = Ah;
       r.out = Ah;
-      HIP_TRY(launch_row_fwd(32, r, (int)pl->L1, (int)pl->L2, stream));
+      rows.j[rows.n++] = r;
       r.in = Bh;
       r.out = Bh;
-      HIP_TRY(launch_row_fwd(32, r, (int)pl->L1, (int)pl->L2, stream));
+      rows.j[rows.n++] = r;
+      HIP_TRY(launch_row_fwd_jobs(32, rows, (int)pl->L1, (int)pl->L2, stream));
     } else {
       const uint32_t rp = reduce ? (uint32_t)p : 0u;
       HIP_TRY(launch_copy_rows(Ah, N, N, (const uint32_t*)A, d, d, (uint32_t)n2, stream, rp));

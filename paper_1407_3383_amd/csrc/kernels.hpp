@@ -81,6 +81,7 @@ struct PassJobs {
 hipError_t launch_col_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_col_inv_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_row_polymul_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
+hipError_t launch_row_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_col_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_col_inv(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);
 hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream);

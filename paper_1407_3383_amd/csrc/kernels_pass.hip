@@ -645,6 +645,9 @@ static hipError_t launch_row_kind(int word_bits, const PassJobs& a, int L1, int 
 hipError_t launch_row_fwd(int word_bits, const PassArgs& a, int L1, int L2, hipStream_t stream) {
   return launch_row_kind<0>(word_bits, one_job(a), L1, L2, stream);
 }
+hipError_t launch_row_fwd_jobs(int word_bits, const PassJobs& a, int L1, int L2, hipStream_t stream) {
+  return launch_row_kind<0>(word_bits, a, L1, L2, stream);
+}
 hipError_t launch_row_inv(int word_bits, const PassArgs& a, int L1, int L2, bool scale_ninv, hipStream_t stream) {
   (void)scale_ninv;  // the caller passes the twist table with n^-1 folded in when asked
   return launch_row_kind<1>(word_bits, one_job(a), L1, L2, stream);
