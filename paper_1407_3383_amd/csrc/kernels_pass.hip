@@ -161,6 +161,7 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
       }
     }
     if (staged) {
+      // the tile is in LDS already
     } else if (vec4) {
       // runs of 4 columns as one 16-byte (8-byte for 16-bit limbs) access per thread
       const int lc4 = LC - 2;
@@ -234,6 +235,7 @@ __device__ void col_wave_body(const PassArgs& A, T* s, uint64_t tile, int L2, co
       }
     }
     if (staged) {
+      // the tile is in LDS already
     } else if (vec4) {
       const int lc4 = LC - 2;
 #pragma unroll 2
@@ -374,7 +376,7 @@ __device__ void row_wave_body(const PassArgs& A, T* sa, T* sb, uint64_t rowid, c
         vin[i][0][cc] = ina[j];
         if constexpr (KIND == 2) vin[i][1][cc] = inb[j];
       }
-    __builtin_amdgcn_sched_barrier(0);  // keeps the scheduler from moving the loads below
+    __builtin_amdgcn_sched_barrier(0);  // the machine scheduler keeps the loads above this point
     TwPair<T> wf[C > 1 ? C - 1 : 1];
     if constexpr (R > 0) cluster_twiddles<T, R, true, true>(wf, tw, 0, 0, 0u, 0u);
     TwPair<T> D[C];
