@@ -272,6 +272,7 @@ __device__ __forceinline__ void polymul_item_wave(const FusedItem& it_in, T* sa,
   // partial is completed from the zero coefficients when lam < nsub (d = 2, lam = 3)
   const int lam = (int)((lc + S - 1) / S < (uint64_t)nsub ? (lc + S - 1) / S : (uint64_t)nsub);
   T* const sv2[2] = {sa, sb};
+  // the wave-local rounds request their twiddles a round ahead (fwd_W / inv_W with PF)
   constexpr bool kWavePF = true;
 
   // G' (top inverse stages) of sub-problem hp on the thread's clusters, with its
