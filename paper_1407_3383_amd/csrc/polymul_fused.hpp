@@ -595,7 +595,8 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
   };
 
   request(a, la);
-  constexpr bool kW15PF = false;  // (the twiddles requested ahead push the spills from 124 to 312 bytes)
+  // (the wave-local rounds here do not request their twiddles ahead: with the
+  // operand a's transform held in registers that would spill 312 bytes per lane)
   for (int h = 0; h < 2; ++h) {
     // ---- A: fold, top stages, wave-local rounds kept in registers
     top_forward(h, a, la, false);
@@ -605,7 +606,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
     for (int k = 0; k < 2; ++k) {
       T* const sv1[1] = {sa};
       T x[1][16];
-      fwd_W<T, LAZY, 1, M, kW15PF>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
+      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
 #pragma unroll
       for (int i = 0; i < 16; ++i) xa[k][i] = x[0][i];
     }
@@ -618,9 +619,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
     for (int k = 0; k < 2; ++k) {
       T* const sv1[1] = {sa};
       T x[1][16];
-      fwd_W<T, LAZY, 1, M, kW15PF>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
-      InvWTw<T> itw;
-      if constexpr (kW15PF) inv_W_twiddles<T, M>(itw, d, (uint32_t)h, twi, wave + 16 * k);
+      fwd_W<T, LAZY, 1, M>(ar, sv1, d, (uint32_t)h, tw, x, wave + 16 * k);
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         T xv = xa[k][i], yv = x[0][i];
@@ -634,7 +633,7 @@ __device__ __forceinline__ void polymul_item_w15(const FusedItem& it_in, T* sa, 
         if constexpr (LAZY != kLazy) z = ar.red1(z);
         x[0][i] = z;
       }
-      inv_W<T, LAZY, M, kW15PF>(ar, sa, d, (uint32_t)h, twi, x[0], wave + 16 * k, &itw);
+      inv_W<T, LAZY, M>(ar, sa, d, (uint32_t)h, twi, x[0], wave + 16 * k);
     }
     __syncthreads();
     // ---- G': top 5 inverse stages; the next sub-problem's a is requested first
